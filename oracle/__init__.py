@@ -1,0 +1,20 @@
+"""FP64 CPU oracle of the modal DG shallow-water right-hand side on the sphere.
+
+TEST INFRASTRUCTURE.  This package is a plain, slow, dense NumPy
+implementation written directly from the paper's equations (section 2).  It
+exists to check the HIP path: only the tests, the smoke check and the CPU
+baseline leg of the benchmark may import it.  The product path (the C-ABI
+library and its Python binding) never imports, calls or falls back to it,
+and this package imports nothing from the product.
+
+Every function here is pinned by tests against facts that do not come from
+the oracle itself (quadrature exactness, closed forms, a textbook first-order
+finite-volume scheme at r = 0, lake at rest, conservation, symmetries,
+convergence of the operator on smooth fields, Runge-Kutta stability
+polynomials and the paper's printed Butcher tableaux).
+"""
+from .basis import gauss_legendre, legendre
+from .sphere import SphereDG
+from .timestep import ssp_rk3, butcher_step
+
+__all__ = ["gauss_legendre", "legendre", "SphereDG", "ssp_rk3", "butcher_step"]
