@@ -1,0 +1,147 @@
+/*
+ * dgsw.h -- C ABI of libdgsw, the modal Discontinuous Galerkin right-hand
+ * side of the shallow-water equations on a latitude-longitude element mesh
+ * of the sphere, and its explicit Runge-Kutta stage loop, for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The method (Szenes, Discacciati, Bonaventura, Sawyer, "Domain-specific
+ * implementation of high-order Discontinuous Galerkin methods in spherical
+ * geometry", arXiv:2303.11767):
+ *   - section 2, the conservative system d_t U + d_lambda F + d_theta G = S
+ *     with U = (h, hu, hv) cos(theta), periodic in longitude, zero flux
+ *     through the poles;
+ *   - section 2, equation "dg_parts" (weak form), equation "rusanov"
+ *     (numerical flux), equation "basis_expansion" (modal Legendre basis of
+ *     full tensor degree r), equation "ode" (M dq/dt = h(q)) and the
+ *     cos(theta)-weighted local mass matrix;
+ *   - section 2, Table "Butcher" (explicit Runge-Kutta tableaux).
+ *
+ * Conventions shared by every call:
+ *   - State layout q[E][3][N], E = n_lon * n_lat elements, element
+ *     e = j * n_lon + i (j = 0 is the southernmost row, i = 0 starts at
+ *     longitude 0), variables (h, hu, hv), N = (r+1)^2 modes with mode
+ *     m = b * (r+1) + a (a: longitude degree, b: latitude degree) of the
+ *     orthonormal basis phi_m(xi, eta) = P~_a(xi) P~_b(eta),
+ *     P~_a = sqrt((2a+1)/2) P_a.
+ *   - Every state pointer (q, dqdt, work, fhat) is caller-owned DEVICE
+ *     memory of the context's dtype, contiguous, 16-byte aligned.  The
+ *     library never allocates or frees caller state.
+ *   - Work is enqueued on the caller's hipStream_t (passed as void*; NULL is
+ *     the null stream).  Calls return as soon as the work is enqueued, except
+ *     dg_mass, which synchronises the stream.
+ *   - Every function returns DG_OK (0) or a negative DG_E* code; nothing is
+ *     thrown across the ABI.  dg_last_error() gives a message for the last
+ *     failure on the calling thread.
+ *   - A context is not used by two host threads at once.
+ */
+#ifndef DGSW_H
+#define DGSW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DG_ABI_VERSION 1
+
+typedef struct dg_ctx dg_ctx;
+
+enum { DG_F64 = 0, DG_F32 = 1 };
+
+/* Latitude factor of the pressure-metric source -g h^2 sin(theta) / (2R).
+ * BALANCED replaces sin(theta) at the quadrature nodes by the degree-r
+ * polynomial that makes the discrete integration by parts of the pressure
+ * exact (a lake at rest has a zero right-hand side); POINTWISE keeps
+ * sin(theta). */
+enum { DG_METRIC_BALANCED = 0, DG_METRIC_POINTWISE = 1 };
+
+/* Rusanov stabilisation alpha (equation "rusanov"): LOCAL takes, at every
+ * edge quadrature point, the larger of |u_n| + sqrt(g h) over the two
+ * sides; GLOBAL uses the fixed speed dg_mesh_desc.alpha [m/s]. */
+enum { DG_ALPHA_LOCAL = 0, DG_ALPHA_GLOBAL = 1 };
+
+/* Runge-Kutta schemes of Table "Butcher": RK1 (forward Euler), RK2 (Heun),
+ * RK3 (the third tableau, SSP), each applied in Shu-Osher form. */
+enum { DG_SSP_RK1 = 1, DG_SSP_RK2 = 2, DG_SSP_RK3 = 3 };
+
+enum {
+  DG_OK = 0,
+  DG_EINVAL = -1,       /* bad argument: null, misaligned, out of range     */
+  DG_EDTYPE = -2,       /* dtype not DG_F64 / DG_F32                          */
+  DG_ENOMEM = -3,       /* device allocation of the context tables failed     */
+  DG_EHIP = -4,         /* a HIP runtime call or kernel launch failed         */
+  DG_ENONFINITE = -5,   /* dg_mass found a NaN or Inf in the state            */
+  DG_EUNSUPPORTED = -6  /* valid but not supported (e.g. order > 7)           */
+};
+
+typedef struct {
+  int32_t abi_version;  /* must be DG_ABI_VERSION                                     */
+  int32_t n_lon;        /* elements in longitude (periodic), >= 1                     */
+  int32_t n_lat;        /* elements in latitude, pole to pole, >= 1                   */
+  int32_t order;        /* polynomial degree r in each direction, 0..7                */
+  int32_t dtype;        /* DG_F64 or DG_F32: state, right-hand side and arithmetic    */
+  int32_t metric;       /* DG_METRIC_*                                                 */
+  int32_t alpha_mode;   /* DG_ALPHA_*                                                  */
+  int32_t reserved;     /* must be 0                                                   */
+  double alpha;         /* [m/s], used iff alpha_mode == DG_ALPHA_GLOBAL, >= 0         */
+  double radius;        /* sphere radius R [m], > 0                                    */
+  double gravity;       /* g [m/s^2], > 0                                              */
+  double omega;         /* rotation rate Omega [1/s]; Coriolis f = 2 Omega sin(theta) */
+  double h_ref;         /* reference depth H [m] >= 0.  When > 0 the kernels evaluate  */
+                        /* h as H + (h - H) and the pressure as g (h^2 - H^2)/2, a     */
+                        /* roundoff-only change under the BALANCED metric (a constant  */
+                        /* pressure then contributes exactly zero).  Rejected with     */
+                        /* POINTWISE.  0 disables it.                                  */
+} dg_mesh_desc;
+
+/* Build a context: host precompute in FP64 (Gauss-Legendre nodes and weights,
+ * Legendre values and derivatives, per-latitude-row inverse mass matrices
+ * folded with the quadrature tables, metric factors), copied to the device
+ * on hip_stream.  Allocates only the context's own tables.  On success
+ * *out is a new context; on failure *out is NULL. */
+int dg_init_mesh(const dg_mesh_desc *desc, void *hip_stream, dg_ctx **out);
+
+/* Release a context and its device tables.  NULL is accepted.  The caller
+ * must make sure no enqueued work still uses the context. */
+int dg_free(dg_ctx *ctx);
+
+/* Number of scalars in one state buffer: E * 3 * N. */
+int dg_state_size(const dg_ctx *ctx, int64_t *n_values);
+
+/* Number of scalars the `work` argument of dg_rk_step must hold for the
+ * scheme (2 state buffers for RK2/RK3, 1 for RK1). */
+int dg_work_size(const dg_ctx *ctx, int32_t scheme, int64_t *n_values);
+
+/* dqdt = M^-1 h(q) (+ fhat if a forcing is set): equation "ode".  q and dqdt
+ * must not overlap. */
+int dg_rhs(dg_ctx *ctx, const void *q, void *dqdt, void *hip_stream);
+
+/* Advance q in place by nsteps >= 0 steps of size dt of the scheme (Shu-Osher
+ * form; for RK3: q1 = q + dt L(q); q2 = 3/4 q + 1/4 (q1 + dt L(q1));
+ * q <- 1/3 q + 2/3 (q2 + dt L(q2))).  work: dg_work_size scalars of scratch,
+ * not overlapping q; its contents are undefined afterwards. */
+int dg_rk_step(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme,
+               int32_t nsteps, void *hip_stream);
+
+/* out[v] = R^2 * integral over the sphere of q_v cos(theta) dlambda dtheta,
+ * v in (h, hu, hv), evaluated exactly for the discrete state with the same
+ * mass matrix that is inverted (phi_00 = 1/2, so an element contributes
+ * 2 (M q)_00).  Accumulated in FP64 in a fixed order (deterministic).
+ * Synchronises hip_stream.  Returns DG_ENONFINITE (out still written) if any
+ * state value is NaN or Inf.  out is a HOST pointer to 3 doubles. */
+int dg_mass(dg_ctx *ctx, const void *q, double out[3], void *hip_stream);
+
+/* Set (or clear with NULL) a modal forcing fhat[E][3][N] (device, ctx dtype)
+ * that every right-hand side evaluation adds to M^-1 h(q); used for
+ * manufactured solutions.  The pointer is borrowed: it must stay valid while
+ * it is set. */
+int dg_set_forcing(dg_ctx *ctx, const void *fhat);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGSW_H */

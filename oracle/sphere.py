@@ -211,6 +211,73 @@ class SphereDG:
                                      - np.einsum("pm,jivp->jivm", self.ES, w * G_S)))
         return vol - surf
 
+    def rhs_scale(self, q):
+        """Size of the terms that are summed into each entry of rhs(q): the
+        same computation with every term replaced by its absolute value
+        (nodal fluxes and sources, both Rusanov halves and the dissipation,
+        |M^-1|).  Rounding in any evaluation order is a small multiple of
+        eps times this, entry by entry, so it is the scale of a
+        componentwise comparison of two floating-point evaluations.  It is
+        large where terms cancel: near the poles the longitude-flux
+        difference is divided by the small cos(theta)-weighted element area.
+        """
+        q = self.grid(q)
+        R, g = self.R, self.g
+        Q = np.einsum("km,jivm->jivk", np.abs(self.V), np.abs(q))
+        Qs = np.einsum("km,jivm->jivk", self.V, q)
+        h, hu, hv = np.abs(Qs[:, :, 0]), np.abs(Qs[:, :, 1]), np.abs(Qs[:, :, 2])
+        hmag = Q[:, :, 0]
+        cosk = self.cos_node[:, self.sk][:, None, :]
+        sink = np.abs(self.sin_node[:, self.sk])[:, None, :]
+        stk = np.abs(self.stilde[:, self.sk])[:, None, :]
+        u, v = hu / h, hv / h
+        pres = 0.5 * g * hmag * hmag
+        F = np.stack([Q[:, :, 1], hu * u + pres, hu * v], axis=2) / R
+        G = cosk[:, :, None] * np.stack([Q[:, :, 2], hu * v, hv * v + pres], axis=2) / R
+        cor = 2.0 * abs(self.omega) * sink * cosk + u * sink / R
+        S = np.stack([np.zeros_like(h), cor * hv, pres * stk / R + cor * hu], axis=2)
+        W = self.Wq
+        vol = (0.5 * self.dth * np.einsum("km,jivk->jivm", np.abs(self.DX), W * F)
+               + 0.5 * self.dlam * np.einsum("km,jivk->jivm", np.abs(self.DY), W * G)
+               + 0.25 * self.dlam * self.dth * np.einsum("km,jivk->jivm", np.abs(self.V), W * S))
+        tr = {k: np.einsum("sm,jivm->jivs", getattr(self, k), q) for k in ("EE", "EW", "EN", "ES")}
+        trm = {k: np.einsum("sm,jivm->jivs", np.abs(getattr(self, k)), np.abs(q))
+               for k in ("EE", "EW", "EN", "ES")}
+
+        def half(qt, qmag, lam):
+            # one side's share of |F^|: half its flux (pressure from the
+            # term magnitude of h) plus half the dissipation alpha |q|
+            hh = np.abs(qt[..., 0, :])
+            mu, mv = np.abs(qt[..., 1, :]), np.abs(qt[..., 2, :])
+            p = 0.5 * g * qmag[..., 0, :] ** 2
+            speed = (mu if lam else mv) / hh + np.sqrt(g * hh)
+            if lam:
+                f = np.stack([qmag[..., 1, :], mu * mu / hh + p, mu * mv / hh], axis=-2)
+            else:
+                f = np.stack([qmag[..., 2, :], mu * mv / hh, mv * mv / hh + p], axis=-2)
+            return 0.5 * f + 0.5 * speed[..., None, :] * qmag
+
+        F_E = (half(tr["EE"], trm["EE"], True)
+               + half(np.roll(tr["EW"], -1, axis=1), np.roll(trm["EW"], -1, axis=1), True)) / R
+        F_W = np.roll(F_E, 1, axis=1)
+        G_edge = np.zeros((self.n_lat + 1, self.n_lon, 3, self.n))
+        if self.n_lat > 1:
+            ce = self.cos_edge[1:-1, None, None, None]
+            G_edge[1:-1] = ce * (half(tr["EN"][:-1], trm["EN"][:-1], False)
+                                 + half(tr["ES"][1:], trm["ES"][1:], False)) / R
+        G_N, G_S = G_edge[1:], G_edge[:-1]
+        w = self.w
+        surf = (0.5 * self.dth * (np.einsum("sm,jivs->jivm", np.abs(self.EE), w * F_E)
+                                  + np.einsum("sm,jivs->jivm", np.abs(self.EW), w * F_W))
+                + 0.5 * self.dlam * (np.einsum("pm,jivp->jivm", np.abs(self.EN), w * G_N)
+                                     + np.einsum("pm,jivp->jivm", np.abs(self.ES), w * G_S)))
+        tot = vol + surf
+        out = np.empty_like(tot)
+        for j in range(self.n_lat):
+            Mi = np.abs(np.linalg.inv(self.M[j]))
+            out[j] = np.einsum("mn,ivn->ivm", Mi, tot[j])
+        return out.reshape(self.E, 3, self.N)
+
     def rhs(self, q):
         """dq/dt = M^-1 h(q) (+ the optional modal forcing), shape (E, 3, N)."""
         res = self.residual(q)

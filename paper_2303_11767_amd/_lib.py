@@ -1,0 +1,78 @@
+"""ctypes loader of libdgsw.so and the C structures of include/dgsw.h.
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  A missing library is an error, never a fallback.
+"""
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdgsw.so")
+
+DG_ABI_VERSION = 1
+DG_F64, DG_F32 = 0, 1
+DG_METRIC_BALANCED, DG_METRIC_POINTWISE = 0, 1
+DG_ALPHA_LOCAL, DG_ALPHA_GLOBAL = 0, 1
+DG_SSP_RK1, DG_SSP_RK2, DG_SSP_RK3 = 1, 2, 3
+DG_OK, DG_EINVAL, DG_EDTYPE, DG_ENOMEM, DG_EHIP, DG_ENONFINITE, DG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+
+ERROR_NAMES = {
+    DG_EINVAL: "DG_EINVAL", DG_EDTYPE: "DG_EDTYPE", DG_ENOMEM: "DG_ENOMEM",
+    DG_EHIP: "DG_EHIP", DG_ENONFINITE: "DG_ENONFINITE", DG_EUNSUPPORTED: "DG_EUNSUPPORTED",
+}
+
+# every symbol include/dgsw.h declares
+EXPORTS = ("dg_init_mesh", "dg_free", "dg_state_size", "dg_work_size", "dg_rhs",
+           "dg_rk_step", "dg_mass", "dg_set_forcing", "dg_last_error")
+
+
+class DGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("n_lon", ctypes.c_int32),
+                ("n_lat", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("metric", ctypes.c_int32),
+                ("alpha_mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("radius", ctypes.c_double),
+                ("gravity", ctypes.c_double), ("omega", ctypes.c_double),
+                ("h_ref", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libdgsw.so (once) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2303_11767_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+    lib.dg_init_mesh.argtypes = [ctypes.POINTER(MeshDesc), vp, ctypes.POINTER(vp)]
+    lib.dg_free.argtypes = [vp]
+    lib.dg_state_size.argtypes = [vp, i64p]
+    lib.dg_work_size.argtypes = [vp, i32, i64p]
+    lib.dg_rhs.argtypes = [vp, vp, vp, vp]
+    lib.dg_rk_step.argtypes = [vp, vp, vp, ctypes.c_double, i32, i32, vp]
+    lib.dg_mass.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.dg_set_forcing.argtypes = [vp, vp]
+    lib.dg_last_error.argtypes = []
+    lib.dg_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "dg_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(rc):
+    if rc != DG_OK:
+        msg = load().dg_last_error().decode(errors="replace")
+        raise DGError(rc, msg)
+    return rc

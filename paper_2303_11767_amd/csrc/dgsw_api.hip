@@ -1,0 +1,258 @@
+// C ABI of libdgsw (declared in include/dgsw.h).
+#include "dgsw.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dgsw_device.hpp"
+#include "dgsw_tables.hpp"
+
+struct dg_ctx {
+  dg_mesh_desc d;
+  int np = 0, N = 0, E = 0;
+  int64_t state_n = 0;
+  size_t elem_bytes = 0;
+  void *d_glob = nullptr;
+  void *d_rows = nullptr;
+  double *d_mass_w = nullptr;
+  double *d_partial = nullptr;
+  double *d_out4 = nullptr;
+  const void *forcing = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(DG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+void release(dg_ctx *c) {
+  if (!c) return;
+  if (c->d_glob) (void)hipFree(c->d_glob);
+  if (c->d_rows) (void)hipFree(c->d_rows);
+  if (c->d_mass_w) (void)hipFree(c->d_mass_w);
+  if (c->d_partial) (void)hipFree(c->d_partial);
+  if (c->d_out4) (void)hipFree(c->d_out4);
+  delete c;
+}
+
+int validate(const dg_mesh_desc *d) {
+  if (!d) return fail(DG_EINVAL, "desc is NULL");
+  if (d->abi_version != DG_ABI_VERSION) return fail(DG_EINVAL, "abi_version mismatch");
+  if (d->n_lon < 1 || d->n_lat < 1) return fail(DG_EINVAL, "n_lon and n_lat must be >= 1");
+  if (d->order < 0) return fail(DG_EINVAL, "order must be >= 0");
+  if (d->order > dgsw::kMaxOrder) return fail(DG_EUNSUPPORTED, "order > 7 is not supported");
+  if (d->dtype != DG_F64 && d->dtype != DG_F32) return fail(DG_EDTYPE, "dtype must be DG_F64 or DG_F32");
+  if (d->metric != DG_METRIC_BALANCED && d->metric != DG_METRIC_POINTWISE)
+    return fail(DG_EINVAL, "unknown metric");
+  if (d->alpha_mode != DG_ALPHA_LOCAL && d->alpha_mode != DG_ALPHA_GLOBAL)
+    return fail(DG_EINVAL, "unknown alpha_mode");
+  if (d->reserved != 0) return fail(DG_EINVAL, "reserved must be 0");
+  if (!(d->radius > 0.0) || !std::isfinite(d->radius)) return fail(DG_EINVAL, "radius must be > 0");
+  if (!(d->gravity > 0.0) || !std::isfinite(d->gravity)) return fail(DG_EINVAL, "gravity must be > 0");
+  if (!std::isfinite(d->omega)) return fail(DG_EINVAL, "omega must be finite");
+  if (!(d->h_ref >= 0.0) || !std::isfinite(d->h_ref)) return fail(DG_EINVAL, "h_ref must be >= 0");
+  if (d->h_ref != 0.0 && d->metric != DG_METRIC_BALANCED)
+    return fail(DG_EINVAL, "h_ref > 0 requires DG_METRIC_BALANCED");
+  if (d->alpha_mode == DG_ALPHA_GLOBAL && (!(d->alpha >= 0.0) || !std::isfinite(d->alpha)))
+    return fail(DG_EINVAL, "alpha must be >= 0 with DG_ALPHA_GLOBAL");
+  const int64_t np = d->order + 1;
+  const int64_t vals = (int64_t)d->n_lon * d->n_lat * 3 * np * np;
+  if (vals >= (int64_t(1) << 31)) return fail(DG_EINVAL, "state exceeds 2^31 values");
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dg_last_error(void) { return g_err.c_str(); }
+
+int dg_init_mesh(const dg_mesh_desc *desc, void *hip_stream, dg_ctx **out) {
+  if (!out) return fail(DG_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(desc);
+  if (rc != DG_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+
+  dgsw::HostTables t;
+  const char *msg = "";
+  if (!dgsw::build_tables(desc->n_lon, desc->n_lat, desc->order,
+                          desc->metric == DG_METRIC_BALANCED ? 0 : 1, desc->radius, t, &msg))
+    return fail(DG_EINVAL, msg);
+
+  dg_ctx *c = new dg_ctx();
+  c->d = *desc;
+  c->np = desc->order + 1;
+  c->N = c->np * c->np;
+  c->E = desc->n_lon * desc->n_lat;
+  c->state_n = (int64_t)c->E * 3 * c->N;
+  c->elem_bytes = desc->dtype == DG_F64 ? 8 : 4;
+
+  const int dt = desc->dtype == DG_F64 ? 0 : 1;
+  const size_t gb = dgsw::glob_bytes(dt, c->np);
+  const size_t rb = dgsw::rows_bytes(dt, c->np, desc->n_lat);
+  std::vector<unsigned char> hg(gb), hr(rb);
+  dgsw::fill_glob(dt, c->np, t, desc->gravity, desc->radius, desc->omega, desc->h_ref,
+                  desc->alpha_mode == DG_ALPHA_GLOBAL ? desc->alpha : 0.0, hg.data());
+  dgsw::fill_rows(dt, c->np, t, hr.data());
+
+  hipError_t e;
+  if ((e = hipMalloc(&c->d_glob, gb)) != hipSuccess ||
+      (e = hipMalloc(&c->d_rows, rb)) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void **>(&c->d_mass_w), t.mass_w.size() * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void **>(&c->d_partial), dgsw::mass_blocks() * 4 * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void **>(&c->d_out4), 4 * sizeof(double))) != hipSuccess) {
+    release(c);
+    return fail(DG_ENOMEM, std::string("hipMalloc of context tables: ") + hipGetErrorString(e));
+  }
+  if ((e = hipMemcpyAsync(c->d_glob, hg.data(), gb, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(c->d_rows, hr.data(), rb, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(c->d_mass_w, t.mass_w.data(), t.mass_w.size() * sizeof(double),
+                          hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess) {
+    release(c);
+    return hip_fail(e, "upload of context tables");
+  }
+  *out = c;
+  return DG_OK;
+}
+
+int dg_free(dg_ctx *ctx) {
+  release(ctx);
+  return DG_OK;
+}
+
+int dg_state_size(const dg_ctx *ctx, int64_t *n_values) {
+  if (!ctx || !n_values) return fail(DG_EINVAL, "NULL argument");
+  *n_values = ctx->state_n;
+  return DG_OK;
+}
+
+int dg_work_size(const dg_ctx *ctx, int32_t scheme, int64_t *n_values) {
+  if (!ctx || !n_values) return fail(DG_EINVAL, "NULL argument");
+  switch (scheme) {
+    case DG_SSP_RK1: *n_values = ctx->state_n; return DG_OK;
+    case DG_SSP_RK2:
+    case DG_SSP_RK3: *n_values = 2 * ctx->state_n; return DG_OK;
+    default: return fail(DG_EINVAL, "unknown scheme");
+  }
+}
+
+int dg_set_forcing(dg_ctx *ctx, const void *fhat) {
+  if (!ctx) return fail(DG_EINVAL, "ctx is NULL");
+  if (fhat && !aligned16(fhat)) return fail(DG_EINVAL, "fhat must be 16-byte aligned");
+  ctx->forcing = fhat;
+  return DG_OK;
+}
+
+static int stage(dg_ctx *c, const void *q, const void *q0, void *out, int combine, double c0,
+                 double c1, double dt, hipStream_t s) {
+  dgsw::StageLaunch a;
+  a.q = q;
+  a.q0 = q0;
+  a.out = out;
+  a.forcing = c->forcing;
+  a.glob = c->d_glob;
+  a.rows = c->d_rows;
+  a.n_lon = c->d.n_lon;
+  a.n_lat = c->d.n_lat;
+  a.E = c->E;
+  a.alpha_global = c->d.alpha_mode == DG_ALPHA_GLOBAL;
+  a.combine = combine;
+  a.c0 = c0;
+  a.c1 = c1;
+  a.dt = dt;
+  hipError_t e = dgsw::launch_stage(c->d.dtype == DG_F64 ? 0 : 1, c->np, a, s);
+  if (e != hipSuccess) return hip_fail(e, "stage kernel launch");
+  return DG_OK;
+}
+
+int dg_rhs(dg_ctx *ctx, const void *q, void *dqdt, void *hip_stream) {
+  if (!ctx || !q || !dqdt) return fail(DG_EINVAL, "NULL argument");
+  if (!aligned16(q) || !aligned16(dqdt)) return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
+  const size_t bytes = ctx->state_n * ctx->elem_bytes;
+  const char *a = static_cast<const char *>(q);
+  const char *b = static_cast<const char *>(dqdt);
+  if (a < b + bytes && b < a + bytes) return fail(DG_EINVAL, "q and dqdt overlap");
+  return stage(ctx, q, nullptr, dqdt, 0, 0.0, 1.0, 0.0, static_cast<hipStream_t>(hip_stream));
+}
+
+int dg_rk_step(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme, int32_t nsteps,
+               void *hip_stream) {
+  if (!ctx || !q || !work) return fail(DG_EINVAL, "NULL argument");
+  if (!aligned16(q) || !aligned16(work)) return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
+  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
+  int64_t wn = 0;
+  int rc = dg_work_size(ctx, scheme, &wn);
+  if (rc != DG_OK) return rc;
+  const size_t bytes = ctx->state_n * ctx->elem_bytes;
+  {
+    const char *a = static_cast<const char *>(q);
+    const char *b = static_cast<const char *>(work);
+    if (a < b + wn * ctx->elem_bytes && b < a + bytes) return fail(DG_EINVAL, "q and work overlap");
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  char *w0 = static_cast<char *>(work);
+  char *w1 = w0 + bytes;
+  for (int n = 0; n < nsteps; ++n) {
+    switch (scheme) {
+      case DG_SSP_RK1:
+        if ((rc = stage(ctx, q, nullptr, w0, 1, 0.0, 1.0, dt, s)) != DG_OK) return rc;
+        {
+          hipError_t e = hipMemcpyAsync(q, w0, bytes, hipMemcpyDeviceToDevice, s);
+          if (e != hipSuccess) return hip_fail(e, "RK1 copy-back");
+        }
+        break;
+      case DG_SSP_RK2:
+        if ((rc = stage(ctx, q, nullptr, w0, 1, 0.0, 1.0, dt, s)) != DG_OK) return rc;
+        if ((rc = stage(ctx, w0, q, q, 1, 0.5, 0.5, dt, s)) != DG_OK) return rc;
+        break;
+      case DG_SSP_RK3:
+        if ((rc = stage(ctx, q, nullptr, w0, 1, 0.0, 1.0, dt, s)) != DG_OK) return rc;
+        if ((rc = stage(ctx, w0, q, w1, 1, 0.75, 0.25, dt, s)) != DG_OK) return rc;
+        if ((rc = stage(ctx, w1, q, q, 1, 1.0 / 3.0, 2.0 / 3.0, dt, s)) != DG_OK) return rc;
+        break;
+      default:
+        return fail(DG_EINVAL, "unknown scheme");
+    }
+  }
+  return DG_OK;
+}
+
+int dg_mass(dg_ctx *ctx, const void *q, double out[3], void *hip_stream) {
+  if (!ctx || !q || !out) return fail(DG_EINVAL, "NULL argument");
+  if (!aligned16(q)) return fail(DG_EINVAL, "q must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = dgsw::launch_mass(ctx->d.dtype == DG_F64 ? 0 : 1, ctx->np, q, ctx->d_mass_w,
+                                   ctx->d.n_lon, ctx->E, ctx->d_partial, ctx->d_out4, s);
+  if (e != hipSuccess) return hip_fail(e, "mass kernel launch");
+  double h4[4];
+  if ((e = hipMemcpyAsync(h4, ctx->d_out4, sizeof(h4), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(e, "mass copy-out");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "mass synchronise");
+  out[0] = h4[0];
+  out[1] = h4[1];
+  out[2] = h4[2];
+  if (h4[3] != 0.0 || !std::isfinite(h4[0]) || !std::isfinite(h4[1]) || !std::isfinite(h4[2]))
+    return fail(DG_ENONFINITE, "state holds " + std::to_string((long long)h4[3]) + " non-finite values");
+  return DG_OK;
+}
+
+}  // extern "C"

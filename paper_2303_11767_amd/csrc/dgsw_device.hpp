@@ -1,0 +1,76 @@
+// Device-side table layouts and the host-callable launchers of the DG kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dgsw_tables.hpp"
+
+namespace dgsw {
+
+// Tables shared by every element (uploaded once per context, read by
+// wave-uniform addresses, so they arrive through the scalar cache).
+template <typename T, int NP>
+struct GlobTab {
+  T B[NP][NP];   // P~_a(xi_p), [p][a]
+  T D[NP][NP];   // P~'_a(xi_p), [p][a]
+  T Pp[NP];      // P~_a(+1)
+  T Pm[NP];      // P~_a(-1)
+  T w[NP];       // Gauss-Legendre weights
+  T cF;          // 2 / dlambda: longitude volume and edge terms after M^-1
+  T cG;          // 2 / dtheta:  latitude volume and edge terms after M^-1
+  T g;           // gravity
+  T invR;        // 1 / radius
+  T two_omega;   // 2 Omega
+  T href;        // reference depth H (0: off)
+  T two_href;    // 2 H: the (h, mode 00) coefficient of the constant H
+  T alpha;       // fixed Rusanov speed when alpha_global
+};
+
+// Tables of one latitude row (the mass matrix depends on latitude only).
+template <typename T, int NP>
+struct RowTab {
+  T cosn[NP];     // cos(theta) at the row's latitude nodes
+  T sinn[NP];     // sin(theta)
+  T stil[NP];     // pressure-metric factor (balanced s~ or sin)
+  T BM[NP][NP];   // w_s sum_b' Minv[b][b'] P~_b'(eta_s), [s][b]
+  T DM[NP][NP];   // w_s sum_b' Minv[b][b'] P~'_b'(eta_s), [s][b]
+  T MN[NP];       // sum_b' Minv[b][b'] P~_b'(+1)
+  T MS[NP];       // sum_b' Minv[b][b'] P~_b'(-1)
+  T ctop;         // cos(theta) at the north edge (0 at the pole)
+  T cbot;         // cos(theta) at the south edge (0 at the pole)
+};
+
+struct StageLaunch {
+  const void *q;        // state L is evaluated on
+  const void *q0;       // q^n of the stage combination (may alias out)
+  void *out;            // result
+  const void *forcing;  // optional modal forcing (may be null)
+  const void *glob;     // GlobTab<T, NP> on the device
+  const void *rows;     // RowTab<T, NP>[n_lat] on the device
+  int n_lon, n_lat, E;
+  int alpha_global;
+  int combine;          // 0: out = L(q); 1: out = c0 q0 + c1 (q + dt L(q))
+  double c0, c1, dt;
+};
+
+// dtype 0 = double, 1 = float; np = order + 1.  Returns a hipError_t.
+hipError_t launch_stage(int dtype, int np, const StageLaunch &a, hipStream_t s);
+
+// Upload helpers: convert FP64 host tables to the device layouts.
+// Returns the number of bytes of each table for (dtype, np).
+size_t glob_bytes(int dtype, int np);
+size_t rows_bytes(int dtype, int np, int n_lat);
+void fill_glob(int dtype, int np, const HostTables &t, double g, double radius,
+               double omega, double href, double alpha, void *dst);
+void fill_rows(int dtype, int np, const HostTables &t, void *dst);
+
+// Mass diagnostic: partial sums per block, then one ordered final sum.
+// out4 (device) = (mass_h, mass_hu, mass_hv, count of non-finite values).
+int mass_blocks();
+hipError_t launch_mass(int dtype, int np, const void *q, const double *mass_w,
+                       int n_lon, int E, double *partial, double *out4,
+                       hipStream_t s);
+
+}  // namespace dgsw

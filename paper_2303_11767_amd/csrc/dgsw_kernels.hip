@@ -1,0 +1,522 @@
+// HIP kernels of the modal DG shallow-water right-hand side on the sphere,
+// for gfx950 (64-wide wavefronts).
+//
+// One fused kernel per Runge-Kutta stage.  Work unit: one element, handled by
+// NP = r+1 lanes ("line lanes"); a 64-lane wavefront holds 64/NP elements and
+// is one workgroup.  Lane t of an element owns line t of the element's data in
+// every phase and the phases are joined by transposes through LDS:
+//
+//   load      lane t holds modal row b = t of h, hu, hv (n contiguous values:
+//             coalesced 16-byte loads across the element's lanes)
+//   xi pass   A[p][b=t] = sum_a q[a][t] P~_a(xi_p), and the same at xi = +-1
+//   --- LDS transpose ---
+//   eta pass  lane t = node column p: nodal values Q[t][s] (modal -> quadrature
+//             of h, hu, hv, eq. "basis_expansion") and the north/south traces;
+//             lane t = edge node s: the east/west traces
+//   halo      traces of the four neighbours at the shared edges, each from one
+//             row or column of the neighbour's coefficients (periodic in
+//             longitude, none across a pole)
+//   edges     Rusanov flux (eq. "rusanov") at edge node t of all four edges
+//   volume    fluxes F, G and sources S at the n nodes of column t, contracted
+//             over the latitude nodes with the inverse mass matrix folded in
+//             (per-row tables BM, DM, MN, MS), north/south surface terms added
+//   --- LDS transpose ---
+//   xi pass   lane t = latitude degree b: contraction over the longitude nodes
+//             with P~' (F term) and P~ (G and S terms), east/west surface
+//             terms, giving row b of dq/dt = M^-1 h(q) (eq. "ode")
+//   epilogue  optional forcing, then either dq/dt or the Shu-Osher stage
+//             combination c0 q^n + c1 (q + dt dq/dt), stored as row b.
+//
+// The weak form is that of eq. "dg_parts": volume term of F . grad(phi) plus
+// the source, minus the surface term of the Rusanov flux times phi.  Integrals
+// are in (lambda, theta) coordinates: the longitude volume and edge terms
+// carry dtheta/2, the latitude ones dlambda/2, the source dlambda dtheta/4, and
+// the mass matrix dlambda dtheta/4 times the latitude matrix
+// int P~_b P~_b' cos(theta) deta, whose inverse is folded into the tables
+// (hence the constants 2/dlambda and 2/dtheta).
+#include "dgsw_device.hpp"
+
+#include <cstring>
+#include <type_traits>
+
+namespace dgsw {
+
+template <typename T, int NP>
+struct Shape {
+  static constexpr int N = NP * NP;
+  static constexpr int GPW = 64 / NP;  // elements per wavefront
+  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  // per-element LDS: transposes of the xi pass (incl. the two edge rows),
+  // the neighbour halo exchange, and the second transpose plus edge fluxes
+  static constexpr int SH = cmax(cmax(3 * (NP + 2) * NP, 12 * NP), 6 * NP * NP + 6 * NP);
+};
+
+template <typename T>
+__device__ __forceinline__ T dg_sqrt(T x) { return sqrt(x); }
+template <>
+__device__ __forceinline__ float dg_sqrt<float>(float x) { return sqrtf(x); }
+
+// Rusanov bracket on a constant-longitude edge, without the 1/R factor:
+// (f(q-) + f(q+))/2 - alpha/2 (q+ - q-), f = (hu, hu u + p, hu v),
+// alpha = max(|u| + sqrt(g h)) over both sides (or fixed).  Variable 0 of the
+// traces is h - H, the pressure is g (h^2 - H^2)/2.
+template <typename T>
+__device__ __forceinline__ void rusanov_lambda(const T qm[3], const T qp[3], T H, T g,
+                                               bool fixed, T alpha_fixed, T out[3]) {
+  const T hm = qm[0] + H, hp = qp[0] + H;
+  const T um = qm[1] / hm, up = qp[1] / hp;
+  const T pm = T(0.5) * g * qm[0] * (hm + H), pp = T(0.5) * g * qp[0] * (hp + H);
+  T a = alpha_fixed;
+  if (!fixed) {
+    const T sm = fabs(um) + dg_sqrt(g * hm), sp = fabs(up) + dg_sqrt(g * hp);
+    a = sm > sp ? sm : sp;
+  }
+  const T vm = qm[2] / hm, vp = qp[2] / hp;
+  out[0] = T(0.5) * (qm[1] + qp[1]) - T(0.5) * a * (qp[0] - qm[0]);
+  out[1] = T(0.5) * ((qm[1] * um + pm) + (qp[1] * up + pp)) - T(0.5) * a * (qp[1] - qm[1]);
+  out[2] = T(0.5) * (qm[1] * vm + qp[1] * vp) - T(0.5) * a * (qp[2] - qm[2]);
+}
+
+// Same on a constant-latitude edge, g-flux = (hv, hv u, hv v + p), without
+// the cos(theta_edge)/R factor.
+template <typename T>
+__device__ __forceinline__ void rusanov_theta(const T qm[3], const T qp[3], T H, T g,
+                                              bool fixed, T alpha_fixed, T out[3]) {
+  const T hm = qm[0] + H, hp = qp[0] + H;
+  const T vm = qm[2] / hm, vp = qp[2] / hp;
+  const T pm = T(0.5) * g * qm[0] * (hm + H), pp = T(0.5) * g * qp[0] * (hp + H);
+  T a = alpha_fixed;
+  if (!fixed) {
+    const T sm = fabs(vm) + dg_sqrt(g * hm), sp = fabs(vp) + dg_sqrt(g * hp);
+    a = sm > sp ? sm : sp;
+  }
+  const T um = qm[1] / hm, up = qp[1] / hp;
+  out[0] = T(0.5) * (qm[2] + qp[2]) - T(0.5) * a * (qp[0] - qm[0]);
+  out[1] = T(0.5) * (qm[2] * um + qp[2] * up) - T(0.5) * a * (qp[1] - qm[1]);
+  out[2] = T(0.5) * ((qm[2] * vm + pm) + (qp[2] * vp + pp)) - T(0.5) * a * (qp[2] - qm[2]);
+}
+
+template <typename T, int NP>
+__global__ __launch_bounds__(64) void k_dg_stage(
+    const T *__restrict__ q, const T *q0, T *out, const T *__restrict__ forcing,
+    const GlobTab<T, NP> *__restrict__ gt, const RowTab<T, NP> *__restrict__ rows,
+    int n_lon, int n_lat, int E, int alpha_global, int combine, T c0, T c1, T dt) {
+  using S_ = Shape<T, NP>;
+  constexpr int N = S_::N, GPW = S_::GPW, SH = S_::SH;
+  __shared__ T sh[(GPW + 1) * SH];
+
+  const int lane = threadIdx.x;
+  int g = lane / NP, t = lane - g * NP;
+  const bool idle = g >= GPW;  // the 64 mod NP spare lanes: a dummy LDS slot
+  if (idle) { g = GPW; t = lane - GPW * NP; }
+  int e = blockIdx.x * GPW + g;
+  const bool active = !idle && e < E;
+  if (e >= E) e = E - 1;       // ragged tail: compute on a valid element, store nothing
+  T *S = sh + g * SH;
+
+  const int j = e / n_lon;
+  const int i = e - j * n_lon;
+  const RowTab<T, NP> &rt = rows[j];
+  const T H = gt->href, H2 = gt->two_href, grav = gt->g, invR = gt->invR;
+  const bool fixed = alpha_global != 0;
+  const T alpha = gt->alpha;
+
+  // ---- load own modal rows b = t (unmodified copy kept for the epilogue)
+  const T *qe = q + (size_t)e * 3 * N;
+  T qr[3][NP];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int a = 0; a < NP; ++a) qr[v][a] = qe[v * N + t * NP + a];
+
+  // ---- xi pass: A[v][p][b=t], and the xi = +1 / -1 rows for the E/W traces
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    T qa[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) qa[a] = qr[v][a];
+    if (v == 0 && t == 0) qa[0] -= H2;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      T acc = T(0);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) acc += qa[a] * gt->B[p][a];
+      S[(v * (NP + 2) + p) * NP + t] = acc;
+    }
+    T ae = T(0), aw = T(0);
+#pragma unroll
+    for (int a = 0; a < NP; ++a) { ae += qa[a] * gt->Pp[a]; aw += qa[a] * gt->Pm[a]; }
+    S[(v * (NP + 2) + NP) * NP + t] = ae;
+    S[(v * (NP + 2) + NP + 1) * NP + t] = aw;
+  }
+  __syncthreads();
+
+  // ---- eta pass: nodal values of column p = t; own traces
+  T nd[3][NP], trN[3], trS[3], trE[3], trW[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    T col[NP], ce[NP], cw[NP];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      col[b] = S[(v * (NP + 2) + t) * NP + b];
+      ce[b] = S[(v * (NP + 2) + NP) * NP + b];
+      cw[b] = S[(v * (NP + 2) + NP + 1) * NP + b];
+    }
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      T acc = T(0);
+#pragma unroll
+      for (int b = 0; b < NP; ++b) acc += col[b] * gt->B[s][b];
+      nd[v][s] = acc;
+    }
+    T an = T(0), as = T(0), ae = T(0), aw = T(0);
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      an += col[b] * gt->Pp[b];
+      as += col[b] * gt->Pm[b];
+      ae += ce[b] * gt->B[t][b];
+      aw += cw[b] * gt->B[t][b];
+    }
+    trN[v] = an; trS[v] = as; trE[v] = ae; trW[v] = aw;
+  }
+  __syncthreads();
+
+  // ---- neighbour traces at the shared edges
+  const bool hasN = j < n_lat - 1, hasS = j > 0;
+  const int eE = (i + 1 == n_lon) ? e + 1 - n_lon : e + 1;
+  const int eW = (i == 0) ? e - 1 + n_lon : e - 1;
+  const int eN = hasN ? e + n_lon : e;
+  const int eS = hasS ? e - n_lon : e;
+  {
+    const T *rE = q + (size_t)eE * 3 * N + t * NP;   // row b = t
+    const T *rW = q + (size_t)eW * 3 * N + t * NP;
+    const T *cN = q + (size_t)eN * 3 * N + t;        // column a = t
+    const T *cS = q + (size_t)eS * 3 * N + t;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      T ue = T(0), uw = T(0), vn = T(0), vs = T(0);
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        T xe = rE[v * N + k], xw = rW[v * N + k];
+        T xn = cN[v * N + k * NP], xs = cS[v * N + k * NP];
+        if (v == 0 && t == 0 && k == 0) { xe -= H2; xw -= H2; xn -= H2; xs -= H2; }
+        ue += xe * gt->Pm[k];   // east neighbour seen from its west edge
+        uw += xw * gt->Pp[k];   // west neighbour seen from its east edge
+        vn += xn * gt->Pm[k];   // north neighbour seen from its south edge
+        vs += xs * gt->Pp[k];   // south neighbour seen from its north edge
+      }
+      S[(0 * 3 + v) * NP + t] = ue;
+      S[(1 * 3 + v) * NP + t] = uw;
+      S[(2 * 3 + v) * NP + t] = vn;
+      S[(3 * 3 + v) * NP + t] = vs;
+    }
+  }
+  __syncthreads();
+  T nbE[3], nbW[3], nbN[3], nbS[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    T ae = T(0), aw = T(0), an = T(0), as = T(0);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const T bt = gt->B[t][k];
+      ae += S[(0 * 3 + v) * NP + k] * bt;
+      aw += S[(1 * 3 + v) * NP + k] * bt;
+      an += S[(2 * 3 + v) * NP + k] * bt;
+      as += S[(3 * 3 + v) * NP + k] * bt;
+    }
+    nbE[v] = ae; nbW[v] = aw; nbN[v] = an; nbS[v] = as;
+  }
+  __syncthreads();
+
+  // ---- Rusanov fluxes at edge node t of the four edges (minus = west/south)
+  T FhE[3], FhW[3], GhN[3], GhS[3];
+  rusanov_lambda<T>(trE, nbE, H, grav, fixed, alpha, FhE);
+  rusanov_lambda<T>(nbW, trW, H, grav, fixed, alpha, FhW);
+  rusanov_theta<T>(trN, nbN, H, grav, fixed, alpha, GhN);
+  rusanov_theta<T>(nbS, trS, H, grav, fixed, alpha, GhS);
+  const T fN = hasN ? rt.ctop * invR : T(0);   // zero flux through a pole
+  const T fS = hasS ? rt.cbot * invR : T(0);
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    FhE[v] *= invR; FhW[v] *= invR; GhN[v] *= fN; GhS[v] *= fS;
+  }
+
+  // ---- volume: fluxes and sources at the nodes (p = t, s), contracted over s
+  T ZD[3][NP], ZG[3][NP], ZS[2][NP];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int b = 0; b < NP; ++b) { ZD[v][b] = T(0); ZG[v][b] = T(0); }
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int b = 0; b < NP; ++b) ZS[v][b] = T(0);
+  const T two_omega = gt->two_omega;
+#pragma unroll
+  for (int s = 0; s < NP; ++s) {
+    const T dh = nd[0][s], hu = nd[1][s], hv = nd[2][s];
+    const T h = dh + H;
+    const T rh = T(1) / h;
+    const T u = hu * rh, vv = hv * rh;
+    const T pr = T(0.5) * grav * dh * (h + H);
+    const T c = rt.cosn[s], sn = rt.sinn[s], st = rt.stil[s];
+    const T F0 = hu * invR, F1 = (hu * u + pr) * invR, F2 = hu * vv * invR;
+    const T cR = c * invR;
+    const T G0 = hv * cR, G1 = hv * u * cR, G2 = (hv * vv + pr) * cR;
+    const T C = sn * (two_omega * c + u * invR);
+    const T S1 = C * hv, S2 = -pr * st * invR - C * hu;
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      const T bm = rt.BM[s][b], dm = rt.DM[s][b];
+      ZD[0][b] += F0 * bm; ZD[1][b] += F1 * bm; ZD[2][b] += F2 * bm;
+      ZG[0][b] += G0 * dm; ZG[1][b] += G1 * dm; ZG[2][b] += G2 * dm;
+      ZS[0][b] += S1 * bm; ZS[1][b] += S2 * bm;
+    }
+  }
+  const T wt = gt->w[t], cF = gt->cF, cG = gt->cG;
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      const T zg = ZG[v][b] - (GhN[v] * rt.MN[b] - GhS[v] * rt.MS[b]);
+      const T zs = v == 0 ? T(0) : ZS[v - 1][b];
+      S[((v * 2 + 0) * NP + t) * NP + b] = cF * wt * ZD[v][b];
+      S[((v * 2 + 1) * NP + t) * NP + b] = wt * (cG * zg + zs);
+    }
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    S[6 * NP * NP + (v * 2 + 0) * NP + t] = FhE[v];
+    S[6 * NP * NP + (v * 2 + 1) * NP + t] = FhW[v];
+  }
+  __syncthreads();
+
+  // ---- xi pass back to modes: lane t = latitude degree b
+  const size_t base = (size_t)e * 3 * N + t * NP;
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    T zd[NP], zb[NP];
+    T XE = T(0), XW = T(0);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      zd[p] = S[((v * 2 + 0) * NP + p) * NP + t];
+      zb[p] = S[((v * 2 + 1) * NP + p) * NP + t];
+      const T bms = rt.BM[p][t];
+      XE += S[6 * NP * NP + (v * 2 + 0) * NP + p] * bms;
+      XW += S[6 * NP * NP + (v * 2 + 1) * NP + p] * bms;
+    }
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      T acc = T(0);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) acc += gt->D[p][a] * zd[p] + gt->B[p][a] * zb[p];
+      acc -= cF * (gt->Pp[a] * XE - gt->Pm[a] * XW);
+      if (forcing) acc += forcing[base + v * N + a];
+      if (active) {
+        if (combine) {
+          const T qn = (c0 != T(0)) ? q0[base + v * N + a] : T(0);
+          out[base + v * N + a] = c0 * qn + c1 * (qr[v][a] + dt * acc);
+        } else {
+          out[base + v * N + a] = acc;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ mass
+constexpr int kMassThreads = 256;
+constexpr int kMassBlocks = 512;
+
+int mass_blocks() { return kMassBlocks; }
+
+template <int NT>
+__device__ __forceinline__ void block_sum4(double v[4], double *sh) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sh[k * NT + tid] = v[k];
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if (tid < off)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sh[k * NT + tid] += sh[k * NT + tid + off];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = sh[k * NT];
+}
+
+template <typename T, int NP>
+__global__ __launch_bounds__(kMassThreads) void k_mass_partial(const T *__restrict__ q,
+                                                               const double *__restrict__ mw,
+                                                               int n_lon, int E,
+                                                               double *__restrict__ partial) {
+  constexpr int N = NP * NP;
+  __shared__ double sh[4 * kMassThreads];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int e = blockIdx.x * kMassThreads + threadIdx.x; e < E; e += gridDim.x * kMassThreads) {
+    const int j = e / n_lon;
+    const T *qe = q + (size_t)e * 3 * N;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+#pragma unroll
+      for (int b = 0; b < NP; ++b) acc[v] += mw[j * NP + b] * (double)qe[v * N + b * NP];
+    }
+    for (int k = 0; k < 3 * N; ++k)
+      if (!isfinite((double)qe[k])) acc[3] += 1.0;
+  }
+  block_sum4<kMassThreads>(acc, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) partial[blockIdx.x * 4 + k] = acc[k];
+}
+
+__global__ __launch_bounds__(kMassThreads) void k_mass_final(const double *__restrict__ partial,
+                                                             int nblocks, double *__restrict__ out4) {
+  __shared__ double sh[4 * kMassThreads];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += kMassThreads)
+    for (int k = 0; k < 4; ++k) acc[k] += partial[b * 4 + k];
+  block_sum4<kMassThreads>(acc, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) out4[k] = acc[k];
+}
+
+// ------------------------------------------------------------------ dispatch
+template <typename T, int NP>
+static hipError_t launch_stage_t(const StageLaunch &a, hipStream_t s) {
+  constexpr int GPW = Shape<T, NP>::GPW;
+  const int grid = (a.E + GPW - 1) / GPW;
+  hipLaunchKernelGGL((k_dg_stage<T, NP>), dim3(grid), dim3(64), 0, s,
+                     static_cast<const T *>(a.q), static_cast<const T *>(a.q0),
+                     static_cast<T *>(a.out), static_cast<const T *>(a.forcing),
+                     static_cast<const GlobTab<T, NP> *>(a.glob),
+                     static_cast<const RowTab<T, NP> *>(a.rows), a.n_lon, a.n_lat, a.E,
+                     a.alpha_global, a.combine, T(a.c0), T(a.c1), T(a.dt));
+  return hipGetLastError();
+}
+
+template <typename T, int NP>
+static hipError_t launch_mass_t(const void *q, const double *mw, int n_lon, int E,
+                                double *partial, double *out4, hipStream_t s) {
+  hipLaunchKernelGGL((k_mass_partial<T, NP>), dim3(kMassBlocks), dim3(kMassThreads), 0, s,
+                     static_cast<const T *>(q), mw, n_lon, E, partial);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(kMassThreads), 0, s, partial, kMassBlocks, out4);
+  return hipGetLastError();
+}
+
+// expands to a switch over the runtime (dtype, np) that returns FN<T, NP>(args)
+#define DGSW_DISPATCH(dtype, np, FN, ...)                                              \
+  switch (np) {                                                                       \
+    case 1: return (dtype) == 0 ? FN<double, 1>(__VA_ARGS__) : FN<float, 1>(__VA_ARGS__); \
+    case 2: return (dtype) == 0 ? FN<double, 2>(__VA_ARGS__) : FN<float, 2>(__VA_ARGS__); \
+    case 3: return (dtype) == 0 ? FN<double, 3>(__VA_ARGS__) : FN<float, 3>(__VA_ARGS__); \
+    case 4: return (dtype) == 0 ? FN<double, 4>(__VA_ARGS__) : FN<float, 4>(__VA_ARGS__); \
+    case 5: return (dtype) == 0 ? FN<double, 5>(__VA_ARGS__) : FN<float, 5>(__VA_ARGS__); \
+    case 6: return (dtype) == 0 ? FN<double, 6>(__VA_ARGS__) : FN<float, 6>(__VA_ARGS__); \
+    case 7: return (dtype) == 0 ? FN<double, 7>(__VA_ARGS__) : FN<float, 7>(__VA_ARGS__); \
+    case 8: return (dtype) == 0 ? FN<double, 8>(__VA_ARGS__) : FN<float, 8>(__VA_ARGS__); \
+    default: break;                                                                   \
+  }
+
+hipError_t launch_stage(int dtype, int np, const StageLaunch &a, hipStream_t s) {
+  DGSW_DISPATCH(dtype, np, launch_stage_t, a, s)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mass(int dtype, int np, const void *q, const double *mw, int n_lon, int E,
+                       double *partial, double *out4, hipStream_t s) {
+  DGSW_DISPATCH(dtype, np, launch_mass_t, q, mw, n_lon, E, partial, out4, s)
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ tables
+template <typename T, int NP>
+static void fill_glob_t(const HostTables &t, double g, double radius, double omega, double href,
+                        double alpha, void *dst) {
+  GlobTab<T, NP> G;
+  std::memset(&G, 0, sizeof(G));
+  for (int p = 0; p < NP; ++p)
+    for (int a = 0; a < NP; ++a) { G.B[p][a] = T(t.B[p * NP + a]); G.D[p][a] = T(t.D[p * NP + a]); }
+  for (int a = 0; a < NP; ++a) { G.Pp[a] = T(t.Pp[a]); G.Pm[a] = T(t.Pm[a]); G.w[a] = T(t.w[a]); }
+  G.cF = T(2.0 / t.dlam);
+  G.cG = T(2.0 / t.dth);
+  G.g = T(g);
+  G.invR = T(1.0 / radius);
+  G.two_omega = T(2.0 * omega);
+  G.href = T(href);
+  G.two_href = T(2.0 * href);
+  G.alpha = T(alpha);
+  std::memcpy(dst, &G, sizeof(G));
+}
+
+template <typename T, int NP>
+static void fill_rows_t(const HostTables &t, void *dst) {
+  RowTab<T, NP> *R = static_cast<RowTab<T, NP> *>(dst);
+  for (int j = 0; j < t.n_lat; ++j) {
+    RowTab<T, NP> r;
+    std::memset(&r, 0, sizeof(r));
+    for (int s = 0; s < NP; ++s) {
+      r.cosn[s] = T(t.cosn[j * NP + s]);
+      r.sinn[s] = T(t.sinn[j * NP + s]);
+      r.stil[s] = T(t.stil[j * NP + s]);
+      for (int b = 0; b < NP; ++b) {
+        r.BM[s][b] = T(t.BM[(j * NP + s) * NP + b]);
+        r.DM[s][b] = T(t.DM[(j * NP + s) * NP + b]);
+      }
+      r.MN[s] = T(t.MN[j * NP + s]);
+      r.MS[s] = T(t.MS[j * NP + s]);
+    }
+    r.ctop = T(t.ctop[j]);
+    r.cbot = T(t.cbot[j]);
+    std::memcpy(&R[j], &r, sizeof(r));
+  }
+}
+
+template <typename T, int NP>
+static size_t glob_bytes_t() { return sizeof(GlobTab<T, NP>); }
+template <typename T, int NP>
+static size_t rows_bytes_t(int n_lat) { return sizeof(RowTab<T, NP>) * (size_t)n_lat; }
+template <typename T, int NP>
+static int fill_glob_d(const HostTables &t, double g, double radius, double omega, double href,
+                       double alpha, void *dst) {
+  fill_glob_t<T, NP>(t, g, radius, omega, href, alpha, dst);
+  return 0;
+}
+template <typename T, int NP>
+static int fill_rows_d(const HostTables &t, void *dst) {
+  fill_rows_t<T, NP>(t, dst);
+  return 0;
+}
+
+size_t glob_bytes(int dtype, int np) {
+  DGSW_DISPATCH(dtype, np, glob_bytes_t)
+  return 0;
+}
+
+size_t rows_bytes(int dtype, int np, int n_lat) {
+  DGSW_DISPATCH(dtype, np, rows_bytes_t, n_lat)
+  return 0;
+}
+
+static int fill_glob_i(int dtype, int np, const HostTables &t, double g, double radius,
+                       double omega, double href, double alpha, void *dst) {
+  DGSW_DISPATCH(dtype, np, fill_glob_d, t, g, radius, omega, href, alpha, dst)
+  return -1;
+}
+
+static int fill_rows_i(int dtype, int np, const HostTables &t, void *dst) {
+  DGSW_DISPATCH(dtype, np, fill_rows_d, t, dst)
+  return -1;
+}
+
+void fill_glob(int dtype, int np, const HostTables &t, double g, double radius, double omega,
+               double href, double alpha, void *dst) {
+  (void)fill_glob_i(dtype, np, t, g, radius, omega, href, alpha, dst);
+}
+
+void fill_rows(int dtype, int np, const HostTables &t, void *dst) {
+  (void)fill_rows_i(dtype, np, t, dst);
+}
+
+}  // namespace dgsw

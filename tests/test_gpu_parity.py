@@ -1,0 +1,258 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every case prints what it runs before touching the GPU.  Inputs are the
+seeded band-limited states of dg_inputs; FP32 cases compare with the oracle
+evaluated on the FP32-rounded input (upcast), so input rounding is not
+charged to the kernel.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from dg_inputs import band_limited_state, lake_at_rest_state
+from oracle import SphereDG, butcher_step, ssp_rk3
+from parity_util import TOL, errors
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_11767_amd as dg   # fails loudly if libdgsw.so is missing
+    return dg
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(q, dtype):
+    t = torch.from_numpy(np.ascontiguousarray(q))
+    return t.to(device="cuda", dtype=torch.float64 if dtype == "f64" else torch.float32).contiguous()
+
+
+def make(dg, n_lon, n_lat, order, dtype, **kw):
+    href = kw.pop("h_ref", 1e4 if dtype == "f32" else 0.0)
+    return dg.Mesh(n_lon, n_lat, order, dtype=dtype, h_ref=href, **kw)
+
+
+def oracle_input(q, dtype):
+    return q.astype(np.float32).astype(np.float64) if dtype == "f32" else q
+
+
+def check_rhs(dg, n_lon, n_lat, order, dtype, L, seed, **kw):
+    say("rhs", n_lon, n_lat, order, dtype, L, seed, kw)
+    q, _ = band_limited_state(n_lon, n_lat, order, L, seed)
+    qin = oracle_input(q, dtype)
+    okw = {k: v for k, v in kw.items() if k in ("metric", "alpha_mode", "alpha")}
+    m = SphereDG(n_lon, n_lat, order, **okw)
+    ref, sc = m.rhs(qin), m.rhs_scale(qin)
+    mesh = make(dg, n_lon, n_lat, order, dtype, **kw)
+    got = mesh.rhs(to_dev(q, dtype)).cpu().numpy()
+    comp, norm = errors(got, ref, sc)
+    say("  componentwise", comp, "normwise", norm)
+    assert np.all(np.isfinite(got))
+    assert np.all(comp <= TOL[dtype]), (comp, norm)
+    return comp, norm
+
+
+# ---------------------------------------------------------------- right-hand side
+@pytest.mark.parametrize("order", range(8))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_rhs_every_order_ragged(dg, order, dtype):
+    """13 x 7 elements: several wavefronts and a ragged last one, periodic
+    wrap inside a wavefront, both poles."""
+    check_rhs(dg, 13, 7, order, dtype, L=4, seed=100 + order)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_rhs_c1(dg, dtype):
+    """r = 1, 32 x 16 (the FP64 workload of the smallest configuration)."""
+    check_rhs(dg, 32, 16, 1, dtype, L=6, seed=1)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_rhs_c2(dg, dtype):
+    """r = 3, 180 x 90, band-limited l <= 16: the benchmark workload."""
+    check_rhs(dg, 180, 90, 3, dtype, L=16, seed=2)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_rhs_c3(dg, dtype):
+    """r = 5, 360 x 180, l <= 32."""
+    check_rhs(dg, 360, 180, 5, dtype, L=32, seed=3)
+
+
+def test_rhs_degenerate_meshes(dg):
+    """One row (both edges are poles), one column (the element is its own
+    east and west neighbour), a single element."""
+    check_rhs(dg, 9, 1, 2, "f64", L=3, seed=7)
+    check_rhs(dg, 1, 6, 2, "f64", L=3, seed=8)
+    check_rhs(dg, 1, 1, 1, "f64", L=2, seed=9)
+    check_rhs(dg, 2, 2, 3, "f32", L=2, seed=10)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_rhs_pointwise_and_global_alpha(dg, dtype):
+    check_rhs(dg, 24, 12, 2, dtype, L=6, seed=11, metric="pointwise", alpha_mode="global",
+              alpha=400.0, h_ref=0.0)
+    check_rhs(dg, 24, 12, 3, dtype, L=6, seed=12, alpha_mode="global", alpha=350.0)
+
+
+@pytest.mark.parametrize("order", [1, 3, 5])
+def test_lake_at_rest(dg, order):
+    n_lon, n_lat = 40, 20
+    say("lake", order)
+    q = lake_at_rest_state(n_lon, n_lat, order, 1e4)
+    m = SphereDG(n_lon, n_lat, order)
+    sc = m.rhs_scale(q)
+    d64 = make(dg, n_lon, n_lat, order, "f64").rhs(to_dev(q, "f64")).cpu().numpy()
+    assert (np.abs(d64) / sc).max() <= TOL["f64"]
+    # FP32 with the reference depth equal to the lake depth: exactly zero
+    d32 = make(dg, n_lon, n_lat, order, "f32", h_ref=1e4).rhs(to_dev(q, "f32")).cpu().numpy()
+    assert np.abs(d32).max() == 0.0
+    d64h = make(dg, n_lon, n_lat, order, "f64", h_ref=1e4).rhs(to_dev(q, "f64")).cpu().numpy()
+    assert np.abs(d64h).max() == 0.0
+
+
+def test_forcing_is_added(dg):
+    say("forcing")
+    n_lon, n_lat, order = 16, 8, 2
+    q, _ = band_limited_state(n_lon, n_lat, order, 4, 31)
+    f = np.random.default_rng(5).standard_normal(q.shape)
+    mesh = make(dg, n_lon, n_lat, order, "f64")
+    qd = to_dev(q, "f64")
+    base = mesh.rhs(qd).cpu().numpy()
+    fd = to_dev(f, "f64")
+    mesh.set_forcing(fd)
+    with_f = mesh.rhs(qd).cpu().numpy()
+    mesh.set_forcing(None)
+    np.testing.assert_allclose(with_f, base + f, rtol=0, atol=1e-12 * np.abs(base).max())
+    np.testing.assert_array_equal(mesh.rhs(qd).cpu().numpy(), base)
+
+
+def test_determinism(dg):
+    say("determinism")
+    q, info = band_limited_state(64, 32, 3, 8, 41)
+    for dtype in ("f64", "f32"):
+        mesh = make(dg, 64, 32, 3, dtype)
+        qd = to_dev(q, dtype)
+        a = mesh.rhs(qd).cpu().numpy()
+        b = mesh.rhs(qd).cpu().numpy()
+        assert np.array_equal(a, b)
+        w = mesh.empty_work()
+        q1, q2 = qd.clone(), qd.clone()
+        dt = dg.cfl_time_step(64, 32, 3, info.cmax, 0.1)
+        mesh.rk_step(q1, w, dt, nsteps=5)
+        mesh.rk_step(q2, w, dt, nsteps=5)
+        assert torch.equal(q1, q2)
+
+
+# ---------------------------------------------------------------- time stepping
+def test_ssp_rk3_one_step_parity(dg):
+    """One SSP-RK3 step at 180 x 90, r = 3, FP64: every stage's error is
+    componentwise within the bar, so the step agrees to dt times it."""
+    say("rk3 one step c2")
+    q, info = band_limited_state(180, 90, 3, 16, 2)
+    m = SphereDG(180, 90, 3)
+    dt = m.cfl_time_step(info.cmax, 0.1)
+    ref = m.ssp_rk3_step(q, dt)
+    mesh = make(dg, 180, 90, 3, "f64")
+    qd = to_dev(q, "f64")
+    mesh.rk_step(qd, mesh.empty_work(), dt)
+    got = qd.cpu().numpy()
+    bound = 1e-12 * dt * m.rhs_scale(q) + 4e-16 * np.abs(q)
+    assert np.all(np.abs(got - ref) <= 4 * bound)
+
+
+def test_rk3_c1_100_steps(dg):
+    """32 x 16, r = 1, FP64: 100 SSP-RK3 steps at CFL 0.1 against the oracle;
+    h-mass conserved on the GPU to roundoff."""
+    say("rk3 100 steps c1")
+    q, info = band_limited_state(32, 16, 1, 6, 1)
+    m = SphereDG(32, 16, 1)
+    dt = m.cfl_time_step(info.cmax, 0.1)
+    ref = q.copy()
+    for _ in range(100):
+        ref = m.ssp_rk3_step(ref, dt)
+    mesh = make(dg, 32, 16, 1, "f64")
+    qd = to_dev(q, "f64")
+    m0 = mesh.mass(qd)
+    mesh.rk_step(qd, mesh.empty_work(), dt, nsteps=100)
+    got = qd.cpu().numpy()
+    rel = np.abs(got - ref).max(axis=(0, 2)) / np.abs(ref).max(axis=(0, 2))
+    say("  trajectory relative difference after 100 steps", rel)
+    assert np.all(rel < 1e-10)
+    m1 = mesh.mass(qd)
+    assert abs(m1[0] - m0[0]) <= 1e-13 * abs(m0[0])
+    np.testing.assert_allclose(m1, m.mass(got), rtol=1e-13)
+
+
+@pytest.mark.parametrize("scheme,name", [(1, "RK1"), (2, "RK2")])
+def test_rk1_rk2_match_printed_tableaux(dg, scheme, name):
+    import json
+    say("rk", name)
+    tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "butcher_tableaux.json")))[name]
+    q, info = band_limited_state(24, 12, 2, 5, 51)
+    m = SphereDG(24, 12, 2)
+    dt = m.cfl_time_step(info.cmax, 0.05)
+    ref = butcher_step(m.rhs, q, dt, tab["A"], tab["b"])
+    mesh = make(dg, 24, 12, 2, "f64")
+    qd = to_dev(q, "f64")
+    mesh.rk_step(qd, mesh.empty_work(scheme), dt, scheme=scheme)
+    got = qd.cpu().numpy()
+    bound = 1e-12 * dt * m.rhs_scale(q) + 4e-16 * np.abs(q)
+    assert np.all(np.abs(got - ref) <= 4 * bound)
+
+
+# ---------------------------------------------------------------- mass and failures
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_mass_matches_oracle(dg, dtype):
+    say("mass", dtype)
+    q, _ = band_limited_state(90, 45, 4, 8, 61)
+    m = SphereDG(90, 45, 4)
+    ref = m.mass(oracle_input(q, dtype))
+    got = make(dg, 90, 45, 4, dtype).mass(to_dev(q, dtype))
+    np.testing.assert_allclose(got, ref, rtol=1e-13 if dtype == "f64" else 1e-6,
+                               atol=1e-13 * abs(ref[0]))
+
+
+def test_mass_detects_nonfinite(dg):
+    say("mass nonfinite")
+    q, _ = band_limited_state(16, 8, 2, 4, 71)
+    q[37, 1, 5] = np.nan
+    mesh = make(dg, 16, 8, 2, "f64")
+    with pytest.raises(dg.DGError) as ei:
+        mesh.mass(to_dev(q, "f64"))
+    assert ei.value.code == -5
+    q[37, 1, 5] = np.inf
+    with pytest.raises(dg.DGError):
+        mesh.mass(to_dev(q, "f64"))
+
+
+def test_bad_arguments_rejected(dg):
+    say("bad arguments")
+    import ctypes
+    mesh = make(dg, 8, 4, 1, "f64")
+    lib = mesh._lib
+    x = torch.zeros(mesh.state_size() + 4, dtype=torch.float64, device="cuda")
+    mis = ctypes.c_void_p(x.data_ptr() + 8)
+    ok = ctypes.c_void_p(x.data_ptr())
+    assert lib.dg_rhs(mesh._ctx, mis, ok, None) == -1
+    assert lib.dg_rhs(mesh._ctx, ok, ok, None) == -1                  # overlap
+    assert lib.dg_rhs(mesh._ctx, None, ok, None) == -1
+    assert lib.dg_rk_step(mesh._ctx, ok, ok, 1.0, 3, 1, None) == -1   # overlap
+    assert lib.dg_rk_step(mesh._ctx, ok, ok, 1.0, 9, 1, None) == -1
+    w = torch.zeros(2 * mesh.state_size(), dtype=torch.float64, device="cuda")
+    assert lib.dg_rk_step(mesh._ctx, ok, ctypes.c_void_p(w.data_ptr()), float("nan"), 3, 1, None) == -1
+    with pytest.raises(ValueError):
+        mesh.rhs(torch.zeros(3, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        mesh.rhs(torch.zeros(mesh.shape, dtype=torch.float32, device="cuda"))

@@ -499,3 +499,18 @@ def test_printed_tableaux_stability_polynomials(name, order):
         assert abs(got - expect) < 1e-14
         if name == "RK3":
             assert abs(ssp_rk3(L, np.array([1.0 + 0j]), 1.0)[0] - expect) < 1e-14
+
+
+# ---------------------------------------------------------------- tolerance scale
+@pytest.mark.parametrize("order,n_lon,n_lat", [(1, 32, 16), (3, 40, 20)])
+def test_rhs_scale_bounds_rhs_and_rounding(order, n_lon, n_lat):
+    """The componentwise scale bounds |rhs| (triangle inequality), and a
+    one-ulp random change of the input moves rhs by a few eps of it."""
+    m = SphereDG(n_lon, n_lat, order)
+    q, _ = band_limited_state(n_lon, n_lat, order, 8, seed=21)
+    ref = m.rhs(q)
+    sc = m.rhs_scale(q)
+    assert np.all(np.abs(ref) <= sc * (1 + 1e-12))
+    rng = np.random.default_rng(0)
+    qp = q * (1 + 1.1e-16 * rng.choice([-1.0, 1.0], size=q.shape))
+    assert (np.abs(m.rhs(qp) - ref) / sc).max() < 1e-14
