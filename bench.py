@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Throughput of the modal DG shallow-water SSP-RK3 loop on one GPU.
+
+    python bench.py [--steps K] [--warmup W] [--dtype f64|f32]
+
+Workload: r = 3 (16 modes per variable, 4 x 4 Gauss-Legendre nodes),
+180 x 90 latitude-longitude elements, h = 1e4 m plus a seeded band-limited
+spherical-harmonic perturbation (l <= 16, 100 m) and a non-divergent
+band-limited wind (20 m/s), SSP-RK3 at Courant number 0.1.  A step is one
+SSP-RK3 step (three fused stage kernels).  The state is resident in GPU
+memory before the timed region.
+
+Prints one JSON line: DOF-updates/s (3 E N unknowns times stages per second),
+the roofline of the stage kernel (algorithmic bytes per launch over its
+average launch duration, measured with events on the launch stream), and
+the FP64 oracle timed on the host on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N_LON, N_LAT, ORDER, L_MAX, SEED, CFL = 180, 90, 3, 16, 2, 0.1
+HBM_PEAK_GBS = 8000.0
+METRIC = "DG RHS DOF-updates/s + % HBM roofline; learned r=1 vs plain r=4 at equal err"
+COUNTERS = os.path.join(ROOT, "profiles", "k_dg_stage_r3_180x90_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2303_11767_amd", "csrc", "dgsw_kernels.hip")
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(dtype):
+    """HBM bytes per stage launch from committed rocprofv3 counter runs,
+    or None when they are missing or the kernel source changed since."""
+    try:
+        with open(COUNTERS) as f:
+            for line in f:
+                if line.startswith("{") and '"kernel_sha"' in line:
+                    rec = json.loads(line)
+                    if rec.get("dtype") == dtype and rec.get("kernel_sha") == kernel_sha():
+                        return rec["hbm_bytes_per_launch"]
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(seconds):
+    """The FP64 oracle, as it stands, on one host thread: SSP-RK3 steps of
+    the same workload until about `seconds` of CPU work."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from dg_inputs import band_limited_state
+    from oracle import SphereDG
+    q, info = band_limited_state(N_LON, N_LAT, ORDER, L_MAX, SEED)
+    with threadpool_limits(limits=1):
+        m = SphereDG(N_LON, N_LAT, ORDER)
+        dt = m.cfl_time_step(info.cmax, CFL)
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            q = m.ssp_rk3_step(q, dt)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                break
+    assert np.all(np.isfinite(q))
+    dofs = 3 * m.E * m.N
+    return {"value": dofs * 3 * steps / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} SSP-RK3 steps of the 180x90 r=3 workload in FP64 NumPy, "
+                      f"1 host thread, {el:.1f} s"}
+
+
+def run(args):
+    import numpy as np
+    import torch
+
+    import paper_2303_11767_amd as dg
+    from dg_inputs import band_limited_state
+
+    torch.cuda.set_device(0)
+    q_h, info = band_limited_state(N_LON, N_LAT, ORDER, L_MAX, SEED)
+    href = 1.0e4 if args.dtype == "f32" else 0.0
+    mesh = dg.Mesh(N_LON, N_LAT, ORDER, dtype=args.dtype, h_ref=href)
+    tdt = mesh.dtype
+    q = torch.from_numpy(q_h).to(device="cuda", dtype=tdt).contiguous()
+    work = mesh.empty_work()
+    dt = dg.cfl_time_step(N_LON, N_LAT, ORDER, info.cmax, CFL)
+    dofs = 3 * mesh.E * mesh.N
+    state_bytes = dofs * q.element_size()
+    stream = torch.cuda.current_stream()
+
+    # warmup, then the timed region: exactly K steps
+    mesh.rk_step(q, work, dt, nsteps=args.warmup)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    mesh.rk_step(q, work, dt, nsteps=args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = ev0.elapsed_time(ev1) * 1e-3
+    elapsed = max(gpu_s, 1e-12)
+    mass = mesh.mass(q)
+    if not all(np.isfinite(mass)):
+        raise RuntimeError("state became non-finite")
+
+    # the stage kernel alone: events around every launch of full 3-stage
+    # cycles on the launch stream, and around a block of cycles
+    w0, w1 = work[: q.numel()].view_as(q), work[q.numel():].view_as(q)
+    cycles = args.kernel_cycles
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(3 * cycles)]
+    torch.cuda.synchronize()
+    for c in range(cycles):
+        a, b = evs[3 * c]
+        a.record(stream); mesh.rk_stage(q, None, w0, 0.0, 1.0, dt); b.record(stream)
+        a, b = evs[3 * c + 1]
+        a.record(stream); mesh.rk_stage(w0, q, w1, 0.75, 0.25, dt); b.record(stream)
+        a, b = evs[3 * c + 2]
+        a.record(stream); mesh.rk_stage(w1, q, q, 1.0 / 3.0, 2.0 / 3.0, dt); b.record(stream)
+    torch.cuda.synchronize()
+    per_launch = np.array([a.elapsed_time(b) for a, b in evs]) * 1e-3
+    bl0, bl1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    bl0.record(stream)
+    mesh.rk_step(q, work, dt, nsteps=cycles)
+    bl1.record(stream)
+    torch.cuda.synchronize()
+    block_s = bl0.elapsed_time(bl1) * 1e-3 / (3 * cycles)
+    launch_s = float(per_launch.mean())
+    alg_bytes = 8.0 * state_bytes / 3.0        # mean over the three stages
+    achieved = alg_bytes / launch_s / 1e9
+    traffic = measured_traffic(args.dtype)
+
+    out = {
+        "metric": METRIC,
+        "value": dofs * 3 * args.steps / elapsed,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "plain DG SWE, r=3, 180x90 lat-lon elements, SSP-RK3, CFL 0.1, "
+                               "band-limited l<=16 seed 2",
+                   "n_lon": N_LON, "n_lat": N_LAT, "order": ORDER, "dofs": dofs,
+                   "dt_s": dt, "h_ref": href, "state_bytes": state_bytes},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_dg_stage", "alg_bytes_per_launch": alg_bytes,
+                     "launch_us_events": launch_s * 1e6, "launch_us_block": block_s * 1e6,
+                     "stage_us": [float(per_launch[k::3].mean() * 1e6) for k in range(3)]},
+        "wall_s_timed": wall,
+        "dof_steps_per_s": dofs * args.steps / elapsed,
+    }
+    return out
+
+
+def profile_probe(args):
+    """Short run for rocprofv3 counter passes: a few 3-stage cycles of the
+    stage kernel, then device-to-device copies of a known size (the
+    calibration of the counters)."""
+    import torch
+
+    import paper_2303_11767_amd as dg
+    from dg_inputs import band_limited_state
+    q_h, info = band_limited_state(N_LON, N_LAT, ORDER, L_MAX, SEED)
+    href = 1.0e4 if args.dtype == "f32" else 0.0
+    mesh = dg.Mesh(N_LON, N_LAT, ORDER, dtype=args.dtype, h_ref=href)
+    q = torch.from_numpy(q_h).to(device="cuda", dtype=mesh.dtype).contiguous()
+    work = mesh.empty_work()
+    dt = dg.cfl_time_step(N_LON, N_LAT, ORDER, info.cmax, CFL)
+    mesh.rk_step(q, work, dt, nsteps=args.steps)
+    torch.cuda.synchronize()
+    nbytes = 256 << 20
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "done", "copy_bytes": nbytes, "stage_launches": 3 * args.steps}),
+          flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--kernel-cycles", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-probe", action="store_true",
+                    help="short run for rocprofv3 counter passes (prints no bench line)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build runs the DG loop on a single device "
+              "(multi-GPU sharding is a design note, not an implemented path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.profile_probe:
+        profile_probe(args)
+        return
+    out = run(args)
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

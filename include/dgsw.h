@@ -124,6 +124,14 @@ int dg_rhs(dg_ctx *ctx, const void *q, void *dqdt, void *hip_stream);
 int dg_rk_step(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme,
                int32_t nsteps, void *hip_stream);
 
+/* One Runge-Kutta stage in Shu-Osher form, the building block of
+ * dg_rk_step: out = c0 * q0 + c1 * (q + dt * L(q)), L(q) = M^-1 h(q)
+ * (+ forcing).  q0 may be NULL iff c0 == 0; q0 may be the same buffer as
+ * out (the combination is element-local) but must not partially overlap it;
+ * q must not overlap out. */
+int dg_rk_stage(dg_ctx *ctx, const void *q, const void *q0, void *out, double c0,
+                double c1, double dt, void *hip_stream);
+
 /* out[v] = R^2 * integral over the sphere of q_v cos(theta) dlambda dtheta,
  * v in (h, hu, hv), evaluated exactly for the discrete state with the same
  * mass matrix that is inverted (phi_00 = 1/2, so an element contributes

@@ -100,6 +100,13 @@ class Mesh:
                                _stream_handle(stream)))
         return out
 
+    def rk_stage(self, q, q0, out, c0, c1, dt, stream=None):
+        """out = c0 q0 + c1 (q + dt L(q)); q0 may be None iff c0 == 0."""
+        p0 = self._ptr(q0, "q0") if q0 is not None else None
+        check(self._lib.dg_rk_stage(self._ctx, self._ptr(q, "q"), p0, self._ptr(out, "out"),
+                                    float(c0), float(c1), float(dt), _stream_handle(stream)))
+        return out
+
     def rk_step(self, q, work, dt, scheme=DG_SSP_RK3, nsteps=1, stream=None):
         """Advance q in place by nsteps steps of the scheme."""
         check(self._lib.dg_rk_step(self._ctx, self._ptr(q, "q"),

@@ -23,7 +23,7 @@ ERROR_NAMES = {
 
 # every symbol include/dgsw.h declares
 EXPORTS = ("dg_init_mesh", "dg_free", "dg_state_size", "dg_work_size", "dg_rhs",
-           "dg_rk_step", "dg_mass", "dg_set_forcing", "dg_last_error")
+           "dg_rk_stage", "dg_rk_step", "dg_mass", "dg_set_forcing", "dg_last_error")
 
 
 class DGError(RuntimeError):
@@ -59,6 +59,8 @@ def load():
     lib.dg_state_size.argtypes = [vp, i64p]
     lib.dg_work_size.argtypes = [vp, i32, i64p]
     lib.dg_rhs.argtypes = [vp, vp, vp, vp]
+    lib.dg_rk_stage.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, vp]
     lib.dg_rk_step.argtypes = [vp, vp, vp, ctypes.c_double, i32, i32, vp]
     lib.dg_mass.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.dg_set_forcing.argtypes = [vp, vp]

@@ -236,6 +236,25 @@ int dg_rk_step(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme, int3
   return DG_OK;
 }
 
+int dg_rk_stage(dg_ctx *ctx, const void *q, const void *q0, void *out, double c0, double c1,
+                double dt, void *hip_stream) {
+  if (!ctx || !q || !out) return fail(DG_EINVAL, "NULL argument");
+  if (!q0 && c0 != 0.0) return fail(DG_EINVAL, "q0 is NULL but c0 != 0");
+  if (!aligned16(q) || !aligned16(out) || (q0 && !aligned16(q0)))
+    return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
+  if (!std::isfinite(c0) || !std::isfinite(c1) || !std::isfinite(dt))
+    return fail(DG_EINVAL, "c0, c1 and dt must be finite");
+  const size_t bytes = ctx->state_n * ctx->elem_bytes;
+  const char *a = static_cast<const char *>(q);
+  const char *o = static_cast<const char *>(out);
+  if (a < o + bytes && o < a + bytes) return fail(DG_EINVAL, "q and out overlap");
+  if (q0) {
+    const char *b = static_cast<const char *>(q0);
+    if (b != o && b < o + bytes && o < b + bytes) return fail(DG_EINVAL, "q0 partially overlaps out");
+  }
+  return stage(ctx, q, q0, out, 1, c0, c1, dt, static_cast<hipStream_t>(hip_stream));
+}
+
 int dg_mass(dg_ctx *ctx, const void *q, double out[3], void *hip_stream) {
   if (!ctx || !q || !out) return fail(DG_EINVAL, "NULL argument");
   if (!aligned16(q)) return fail(DG_EINVAL, "q must be 16-byte aligned");
