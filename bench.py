@@ -93,7 +93,7 @@ def run(args):
     tdt = mesh.dtype
     q = torch.from_numpy(q_h).to(device="cuda", dtype=tdt).contiguous()
     work = mesh.empty_work()
-    dt = dg.cfl_time_step(N_LON, N_LAT, ORDER, info.cmax, CFL)
+    dt = dg.cfl_time_step(mesh, info.cmax, CFL)
     dofs = 3 * mesh.E * mesh.N
     state_bytes = dofs * q.element_size()
     stream = torch.cuda.current_stream()
@@ -182,7 +182,7 @@ def profile_probe(args):
     mesh = dg.Mesh(N_LON, N_LAT, ORDER, dtype=args.dtype, h_ref=href)
     q = torch.from_numpy(q_h).to(device="cuda", dtype=mesh.dtype).contiguous()
     work = mesh.empty_work()
-    dt = dg.cfl_time_step(N_LON, N_LAT, ORDER, info.cmax, CFL)
+    dt = dg.cfl_time_step(mesh, info.cmax, CFL)
     mesh.rk_step(q, work, dt, nsteps=args.steps)
     torch.cuda.synchronize()
     nbytes = 256 << 20

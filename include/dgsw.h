@@ -113,6 +113,13 @@ int dg_state_size(const dg_ctx *ctx, int64_t *n_values);
  * scheme (2 state buffers for RK2/RK3, 1 for RK1). */
 int dg_work_size(const dg_ctx *ctx, int32_t scheme, int64_t *n_values);
 
+/* Smallest element width [m] for the Courant number p c dt / H of section 2
+ * (where the paper names H the minimum element diameter):
+ * H = R * min(dtheta, dlambda * min cos(theta) over the latitude quadrature
+ * nodes), i.e. the longitude width at the node nearest a pole.  A caller picks
+ * dt = C H / (max(r,1) c_max). */
+int dg_min_width(const dg_ctx *ctx, double *meters);
+
 /* dqdt = M^-1 h(q) (+ fhat if a forcing is set): equation "ode".  q and dqdt
  * must not overlap. */
 int dg_rhs(dg_ctx *ctx, const void *q, void *dqdt, void *hip_stream);

@@ -306,10 +306,11 @@ class SphereDG:
         return ssp_rk3(self.rhs, np.asarray(q, dtype=np.float64), dt)
 
     def cfl_time_step(self, cmax, cfl):
-        """dt = cfl * H / (max(r,1) c), H the smallest element width (the
-        longitude width at the centre of a pole row), section 2, Courant
-        number p c dt / H."""
-        H = self.R * min(self.dth, self.dlam * np.sin(0.5 * self.dth))
+        """dt = cfl * H / (max(r,1) c): the DG Courant number p c dt / H of
+        section 2.  H is the smallest element width, read as the longitude
+        width at the latitude quadrature node nearest a pole (the width at
+        the centre of the pole row gives unstable runs at cfl 0.1 for r >= 3)."""
+        H = self.R * min(self.dth, self.dlam * self.cos_node.min())
         return cfl * H / (max(self.order, 1) * cmax)
 
     # ------------------------------------------------------------ projection

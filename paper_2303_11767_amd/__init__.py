@@ -17,13 +17,10 @@ __all__ = ["Mesh", "DGError", "cfl_time_step", "DG_SSP_RK1", "DG_SSP_RK2", "DG_S
 RADIUS, GRAVITY, OMEGA = 6.371e6, 9.80616, 7.292e-5
 
 
-def cfl_time_step(n_lon, n_lat, order, cmax, cfl, radius=RADIUS):
-    """dt = cfl * H / (max(r, 1) * c): the DG Courant number p c dt / H of
-    section 2, H the smallest element width (longitude width at the centre
-    of a pole row), c the largest wave speed."""
-    dlam, dth = 2 * math.pi / n_lon, math.pi / n_lat
-    H = radius * min(dth, dlam * math.sin(0.5 * dth))
-    return cfl * H / (max(order, 1) * cmax)
+def cfl_time_step(mesh, cmax, cfl):
+    """dt = cfl * H / (max(r, 1) * c_max), the DG Courant number p c dt / H of
+    section 2, with H the mesh's smallest element width (dg_min_width)."""
+    return cfl * mesh.min_width() / (max(mesh.order, 1) * cmax)
 
 
 def _stream_handle(stream):
@@ -66,6 +63,11 @@ class Mesh:
         n = ctypes.c_int64()
         check(self._lib.dg_state_size(self._ctx, ctypes.byref(n)))
         return n.value
+
+    def min_width(self):
+        w = ctypes.c_double()
+        check(self._lib.dg_min_width(self._ctx, ctypes.byref(w)))
+        return w.value
 
     def work_size(self, scheme=DG_SSP_RK3):
         n = ctypes.c_int64()

@@ -22,7 +22,7 @@ ERROR_NAMES = {
 }
 
 # every symbol include/dgsw.h declares
-EXPORTS = ("dg_init_mesh", "dg_free", "dg_state_size", "dg_work_size", "dg_rhs",
+EXPORTS = ("dg_init_mesh", "dg_free", "dg_state_size", "dg_work_size", "dg_min_width", "dg_rhs",
            "dg_rk_stage", "dg_rk_step", "dg_mass", "dg_set_forcing", "dg_last_error")
 
 
@@ -58,6 +58,7 @@ def load():
     lib.dg_free.argtypes = [vp]
     lib.dg_state_size.argtypes = [vp, i64p]
     lib.dg_work_size.argtypes = [vp, i32, i64p]
+    lib.dg_min_width.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.dg_rhs.argtypes = [vp, vp, vp, vp]
     lib.dg_rk_stage.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, vp]

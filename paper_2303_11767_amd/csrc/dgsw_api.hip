@@ -24,6 +24,7 @@ struct dg_ctx {
   double *d_partial = nullptr;
   double *d_out4 = nullptr;
   const void *forcing = nullptr;
+  double min_width = 0.0;
 };
 
 namespace {
@@ -103,6 +104,12 @@ int dg_init_mesh(const dg_mesh_desc *desc, void *hip_stream, dg_ctx **out) {
   c->E = desc->n_lon * desc->n_lat;
   c->state_n = (int64_t)c->E * 3 * c->N;
   c->elem_bytes = desc->dtype == DG_F64 ? 8 : 4;
+  {
+    double cmin = 1.0;
+    for (double cv : t.cosn) cmin = cv < cmin ? cv : cmin;
+    const double wl = t.dlam * cmin;
+    c->min_width = desc->radius * (t.dth < wl ? t.dth : wl);
+  }
 
   const int dt = desc->dtype == DG_F64 ? 0 : 1;
   const size_t gb = dgsw::glob_bytes(dt, c->np);
@@ -141,6 +148,12 @@ int dg_free(dg_ctx *ctx) {
 int dg_state_size(const dg_ctx *ctx, int64_t *n_values) {
   if (!ctx || !n_values) return fail(DG_EINVAL, "NULL argument");
   *n_values = ctx->state_n;
+  return DG_OK;
+}
+
+int dg_min_width(const dg_ctx *ctx, double *meters) {
+  if (!ctx || !meters) return fail(DG_EINVAL, "NULL argument");
+  *meters = ctx->min_width;
   return DG_OK;
 }
 

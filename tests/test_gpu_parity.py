@@ -149,7 +149,7 @@ def test_determinism(dg):
         assert np.array_equal(a, b)
         w = mesh.empty_work()
         q1, q2 = qd.clone(), qd.clone()
-        dt = dg.cfl_time_step(64, 32, 3, info.cmax, 0.1)
+        dt = dg.cfl_time_step(mesh, info.cmax, 0.1)
         mesh.rk_step(q1, w, dt, nsteps=5)
         mesh.rk_step(q2, w, dt, nsteps=5)
         assert torch.equal(q1, q2)
@@ -256,3 +256,37 @@ def test_bad_arguments_rejected(dg):
         mesh.rhs(torch.zeros(3, dtype=torch.float64, device="cuda"))
     with pytest.raises(ValueError):
         mesh.rhs(torch.zeros(mesh.shape, dtype=torch.float32, device="cuda"))
+
+
+def test_min_width_matches_oracle_time_step(dg):
+    say("min width")
+    for (n_lon, n_lat, order) in [(32, 16, 1), (180, 90, 3), (360, 180, 5), (7, 3, 0)]:
+        mesh = make(dg, n_lon, n_lat, order, "f64")
+        m = SphereDG(n_lon, n_lat, order)
+        assert abs(dg.cfl_time_step(mesh, 333.0, 0.1) - m.cfl_time_step(333.0, 0.1)) <= 1e-13 * m.cfl_time_step(333.0, 0.1)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c2_trajectory_rhs_parity(dg, dtype):
+    """180 x 90, r = 3: 1000 SSP-RK3 steps at CFL 0.1 on the GPU; every 100
+    steps the GPU right-hand side of the current GPU state is compared with
+    the oracle's on the same state; h-mass drift reported and bounded."""
+    say("c2 trajectory", dtype)
+    q, info = band_limited_state(180, 90, 3, 16, 2)
+    m = SphereDG(180, 90, 3)
+    mesh = make(dg, 180, 90, 3, dtype)
+    qd = to_dev(q, dtype)
+    work = mesh.empty_work()
+    dt = dg.cfl_time_step(mesh, info.cmax, 0.1)
+    m0 = mesh.mass(qd)[0]
+    worst = np.zeros(3)
+    for k in range(10):
+        mesh.rk_step(qd, work, dt, nsteps=100)
+        qs = qd.cpu().numpy().astype(np.float64)
+        got = mesh.rhs(qd).cpu().numpy()
+        comp, norm = errors(got, m.rhs(qs), m.rhs_scale(qs))
+        worst = np.maximum(worst, comp)
+    drift = abs(mesh.mass(qd)[0] - m0) / abs(m0)
+    say("  worst componentwise over the trajectory", worst, "h-mass drift", drift)
+    assert np.all(worst <= TOL[dtype])
+    assert drift <= (1e-13 if dtype == "f64" else 1e-5)
