@@ -46,35 +46,114 @@ struct Shape {
   static constexpr int N = NP * NP;
   static constexpr int GPW = 64 / NP;  // elements per wavefront
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
-  // per-element LDS: transposes of the xi pass (incl. the two edge rows),
-  // the neighbour halo exchange, and the second transpose plus edge fluxes
-  static constexpr int SH = cmax(cmax(3 * (NP + 2) * NP, 12 * NP), 6 * NP * NP + 6 * NP);
+  // per-element LDS, two phases sharing one region:
+  //   A/B: the xi-pass rows (n+2 per variable) and the neighbour partial sums
+  //   C/D: the second transpose (two n x n per variable) and the E/W edge fluxes
+  static constexpr int NB = 3 * (NP + 2) * NP;
+  static constexpr int SH = cmax(NB + 12 * NP, 6 * NP * NP + 6 * NP);
+  // tables read with a lane-dependent index, copied to LDS per wavefront:
+  // P~(xi_p) [p][a], weights, and the row's BM [s][b]
+  static constexpr int TB = NP * NP + NP + NP * NP;
+  // byte alignment of one modal row (NP values) given a 16-byte aligned base
+  static constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
+  static constexpr int ROWALIGN = gcd(16, NP * (int)sizeof(T));
 };
 
+// Reciprocal and square root from the hardware approximations.  FP64: v_rcp_f64
+// refined by two Newton steps, and v_rsq_f64 refined by a Goldschmidt step (both
+// within about 1 ulp for the normal, positive depths used here); FP32: v_rcp_f32
+// and v_sqrt_f32 (1 ulp).  The square root only enters the Rusanov speed estimate.
 template <typename T>
-__device__ __forceinline__ T dg_sqrt(T x) { return sqrt(x); }
+__device__ __forceinline__ T dg_rcp(T x);
 template <>
-__device__ __forceinline__ float dg_sqrt<float>(float x) { return sqrtf(x); }
+__device__ __forceinline__ double dg_rcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+template <>
+__device__ __forceinline__ float dg_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <typename T>
+__device__ __forceinline__ T dg_sqrt(T x);
+template <>
+__device__ __forceinline__ double dg_sqrt<double>(double x) {
+  // Goldschmidt iteration from the hardware reciprocal square root (about 29
+  // correct bits): g -> sqrt(x), h -> 1/(2 sqrt(x)), then one residual correction.
+  double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  const double d = __builtin_fma(-g, g, x);
+  return __builtin_fma(d, h, g);
+}
+template <>
+__device__ __forceinline__ float dg_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// LDS ordering between the lanes of one wavefront (a workgroup is one
+// wavefront): LDS requests of a wave complete in order, so a wave-scope fence
+// around a scheduling barrier is enough.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; renumber them so that
+// each XCD gets one contiguous range of rows (its L2 then holds the rows and
+// their north/south neighbours).  Bijective for any count.
+__device__ __forceinline__ int xcd_block(int w, int nb) {
+  const int xcd = w & 7, k = w >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  return xcd < rem ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+}
+
+template <typename T, int NP>
+__device__ __forceinline__ void load_row(const T *p, T (&r)[NP]) {
+  const T *pa = static_cast<const T *>(__builtin_assume_aligned(p, Shape<T, NP>::ROWALIGN));
+#pragma unroll
+  for (int a = 0; a < NP; ++a) r[a] = pa[a];
+}
+
+template <typename T, int NP>
+__device__ __forceinline__ void store_row(T *p, const T (&r)[NP]) {
+  T *pa = static_cast<T *>(__builtin_assume_aligned(p, Shape<T, NP>::ROWALIGN));
+#pragma unroll
+  for (int a = 0; a < NP; ++a) pa[a] = r[a];
+}
+
+// One side of a Rusanov edge: velocity along the edge normal and sqrt(g h).
+// Variable 0 of a trace is h - H; the pressure is g (h^2 - H^2) / 2.
+template <typename T>
+struct Side {
+  T h, rh, u, v, p, c;
+  __device__ __forceinline__ Side(const T q[3], T H, T g) {
+    h = q[0] + H;
+    rh = dg_rcp(h);
+    u = q[1] * rh;
+    v = q[2] * rh;
+    p = T(0.5) * g * q[0] * (h + H);
+    c = dg_sqrt(g * h);
+  }
+};
 
 // Rusanov bracket on a constant-longitude edge, without the 1/R factor:
-// (f(q-) + f(q+))/2 - alpha/2 (q+ - q-), f = (hu, hu u + p, hu v),
-// alpha = max(|u| + sqrt(g h)) over both sides (or fixed).  Variable 0 of the
-// traces is h - H, the pressure is g (h^2 - H^2)/2.
+// (f(q-) + f(q+))/2 - alpha/2 (q+ - q-), f = (hu, hu u + p, hu v).
 template <typename T>
 __device__ __forceinline__ void rusanov_lambda(const T qm[3], const T qp[3], T H, T g,
                                                bool fixed, T alpha_fixed, T out[3]) {
-  const T hm = qm[0] + H, hp = qp[0] + H;
-  const T um = qm[1] / hm, up = qp[1] / hp;
-  const T pm = T(0.5) * g * qm[0] * (hm + H), pp = T(0.5) * g * qp[0] * (hp + H);
+  const Side<T> m(qm, H, g), p(qp, H, g);
   T a = alpha_fixed;
   if (!fixed) {
-    const T sm = fabs(um) + dg_sqrt(g * hm), sp = fabs(up) + dg_sqrt(g * hp);
+    const T sm = fabs(m.u) + m.c, sp = fabs(p.u) + p.c;
     a = sm > sp ? sm : sp;
   }
-  const T vm = qm[2] / hm, vp = qp[2] / hp;
   out[0] = T(0.5) * (qm[1] + qp[1]) - T(0.5) * a * (qp[0] - qm[0]);
-  out[1] = T(0.5) * ((qm[1] * um + pm) + (qp[1] * up + pp)) - T(0.5) * a * (qp[1] - qm[1]);
-  out[2] = T(0.5) * (qm[1] * vm + qp[1] * vp) - T(0.5) * a * (qp[2] - qm[2]);
+  out[1] = T(0.5) * ((qm[1] * m.u + m.p) + (qp[1] * p.u + p.p)) - T(0.5) * a * (qp[1] - qm[1]);
+  out[2] = T(0.5) * (qm[1] * m.v + qp[1] * p.v) - T(0.5) * a * (qp[2] - qm[2]);
 }
 
 // Same on a constant-latitude edge, g-flux = (hv, hv u, hv v + p), without
@@ -82,54 +161,91 @@ __device__ __forceinline__ void rusanov_lambda(const T qm[3], const T qp[3], T H
 template <typename T>
 __device__ __forceinline__ void rusanov_theta(const T qm[3], const T qp[3], T H, T g,
                                               bool fixed, T alpha_fixed, T out[3]) {
-  const T hm = qm[0] + H, hp = qp[0] + H;
-  const T vm = qm[2] / hm, vp = qp[2] / hp;
-  const T pm = T(0.5) * g * qm[0] * (hm + H), pp = T(0.5) * g * qp[0] * (hp + H);
+  const Side<T> m(qm, H, g), p(qp, H, g);
   T a = alpha_fixed;
   if (!fixed) {
-    const T sm = fabs(vm) + dg_sqrt(g * hm), sp = fabs(vp) + dg_sqrt(g * hp);
+    const T sm = fabs(m.v) + m.c, sp = fabs(p.v) + p.c;
     a = sm > sp ? sm : sp;
   }
-  const T um = qm[1] / hm, up = qp[1] / hp;
   out[0] = T(0.5) * (qm[2] + qp[2]) - T(0.5) * a * (qp[0] - qm[0]);
-  out[1] = T(0.5) * (qm[2] * um + qp[2] * up) - T(0.5) * a * (qp[1] - qm[1]);
-  out[2] = T(0.5) * ((qm[2] * vm + pm) + (qp[2] * vp + pp)) - T(0.5) * a * (qp[2] - qm[2]);
+  out[1] = T(0.5) * (qm[2] * m.u + qp[2] * p.u) - T(0.5) * a * (qp[1] - qm[1]);
+  out[2] = T(0.5) * ((qm[2] * m.v + m.p) + (qp[2] * p.v + p.p)) - T(0.5) * a * (qp[2] - qm[2]);
 }
 
+// Wavefront = GPW elements of one latitude row (segment `seg` of row j), so
+// the row's tables are wave-uniform (scalar loads) and the pole tests are
+// uniform branches.  Grid = n_lat * segs workgroups of 64 lanes.
 template <typename T, int NP>
 __global__ __launch_bounds__(64) void k_dg_stage(
     const T *__restrict__ q, const T *q0, T *out, const T *__restrict__ forcing,
     const GlobTab<T, NP> *__restrict__ gt, const RowTab<T, NP> *__restrict__ rows,
-    int n_lon, int n_lat, int E, int alpha_global, int combine, T c0, T c1, T dt) {
+    int n_lon, int n_lat, int segs, int alpha_global, int combine, T c0, T c1, T dt) {
   using S_ = Shape<T, NP>;
-  constexpr int N = S_::N, GPW = S_::GPW, SH = S_::SH;
+  constexpr int N = S_::N, GPW = S_::GPW, SH = S_::SH, NB = S_::NB, TB = S_::TB;
+  __shared__ T tab[TB];
   __shared__ T sh[(GPW + 1) * SH];
 
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int j = blk / segs;
+  const int seg = blk - j * segs;
   const int lane = threadIdx.x;
   int g = lane / NP, t = lane - g * NP;
-  const bool idle = g >= GPW;  // the 64 mod NP spare lanes: a dummy LDS slot
+  const bool idle = g >= GPW;          // the 64 mod NP spare lanes: a dummy LDS slot
   if (idle) { g = GPW; t = lane - GPW * NP; }
-  int e = blockIdx.x * GPW + g;
-  const bool active = !idle && e < E;
-  if (e >= E) e = E - 1;       // ragged tail: compute on a valid element, store nothing
+  const int i_raw = seg * GPW + g;
+  const bool active = !idle && i_raw < n_lon;
+  const int i = i_raw < n_lon ? i_raw : n_lon - 1;   // tail lanes work on a valid element
+  const int e = j * n_lon + i;
   T *S = sh + g * SH;
-
-  const int j = e / n_lon;
-  const int i = e - j * n_lon;
-  const RowTab<T, NP> &rt = rows[j];
+  const RowTab<T, NP> *rt = rows + j;
+  const bool hasN = j < n_lat - 1, hasS = j > 0;
   const T H = gt->href, H2 = gt->two_href, grav = gt->g, invR = gt->invR;
   const bool fixed = alpha_global != 0;
   const T alpha = gt->alpha;
 
-  // ---- load own modal rows b = t (unmodified copy kept for the epilogue)
-  const T *qe = q + (size_t)e * 3 * N;
-  T qr[3][NP];
+  // ---- every global load of the stage, issued up front
+  const size_t row_off = (size_t)t * NP;
+  const size_t base = (size_t)e * 3 * N + row_off;
+  const int eE = (i + 1 == n_lon) ? e + 1 - n_lon : e + 1;
+  const int eW = (i == 0) ? e - 1 + n_lon : e - 1;
+  T qr[3][NP], xE[3][NP], xW[3][NP], xN[3][NP], xS[3][NP];
 #pragma unroll
-  for (int v = 0; v < 3; ++v)
+  for (int v = 0; v < 3; ++v) {
+    load_row<T, NP>(q + base + v * N, qr[v]);
+    load_row<T, NP>(q + (size_t)eE * 3 * N + row_off + v * N, xE[v]);   // row b = t
+    load_row<T, NP>(q + (size_t)eW * 3 * N + row_off + v * N, xW[v]);
+  }
+  if (hasN) {
+    const T *c = q + (size_t)(e + n_lon) * 3 * N + t;                    // column a = t
 #pragma unroll
-    for (int a = 0; a < NP; ++a) qr[v][a] = qe[v * N + t * NP + a];
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) xN[v][k] = c[v * N + k * NP];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) xN[v][k] = T(0);
+  }
+  if (hasS) {
+    const T *c = q + (size_t)(e - n_lon) * 3 * N + t;
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) xS[v][k] = c[v * N + k * NP];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) xS[v][k] = T(0);
+  }
+  {
+    const T *gB = &gt->B[0][0], *gw = &gt->w[0], *rBM = &rt->BM[0][0];
+    for (int k = lane; k < TB; k += 64)
+      tab[k] = k < NP * NP ? gB[k] : (k < NP * NP + NP ? gw[k - NP * NP] : rBM[k - NP * NP - NP]);
+  }
 
-  // ---- xi pass: A[v][p][b=t], and the xi = +1 / -1 rows for the E/W traces
+  // ---- xi pass: A[v][p][b=t] and the xi = +1/-1 rows; neighbour partial sums
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
     T qa[NP];
@@ -148,20 +264,34 @@ __global__ __launch_bounds__(64) void k_dg_stage(
     for (int a = 0; a < NP; ++a) { ae += qa[a] * gt->Pp[a]; aw += qa[a] * gt->Pm[a]; }
     S[(v * (NP + 2) + NP) * NP + t] = ae;
     S[(v * (NP + 2) + NP + 1) * NP + t] = aw;
-  }
-  __syncthreads();
 
-  // ---- eta pass: nodal values of column p = t; own traces
-  T nd[3][NP], trN[3], trS[3], trE[3], trW[3];
+    T ue = T(0), uw = T(0), vn = T(0), vs = T(0);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      T ye = xE[v][k], yw = xW[v][k], yn = xN[v][k], ys = xS[v][k];
+      if (v == 0 && t == 0 && k == 0) { ye -= H2; yw -= H2; yn -= H2; ys -= H2; }
+      ue += ye * gt->Pm[k];   // east neighbour seen from its west edge
+      uw += yw * gt->Pp[k];   // west neighbour seen from its east edge
+      vn += yn * gt->Pm[k];   // north neighbour seen from its south edge
+      vs += ys * gt->Pp[k];   // south neighbour seen from its north edge
+    }
+    S[NB + (0 * 3 + v) * NP + t] = ue;
+    S[NB + (1 * 3 + v) * NP + t] = uw;
+    S[NB + (2 * 3 + v) * NP + t] = vn;
+    S[NB + (3 * 3 + v) * NP + t] = vs;
+  }
+  wave_sync();
+
+  // ---- eta pass: nodal values of column p = t, own and neighbour traces at node t
+  T nd[3][NP], trN[3], trS[3], trE[3], trW[3], nbE[3], nbW[3], nbN[3], nbS[3];
+  T bt[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) bt[k] = tab[t * NP + k];          // P~_k(xi_t)
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
-    T col[NP], ce[NP], cw[NP];
+    T col[NP];
 #pragma unroll
-    for (int b = 0; b < NP; ++b) {
-      col[b] = S[(v * (NP + 2) + t) * NP + b];
-      ce[b] = S[(v * (NP + 2) + NP) * NP + b];
-      cw[b] = S[(v * (NP + 2) + NP + 1) * NP + b];
-    }
+    for (int b = 0; b < NP; ++b) col[b] = S[(v * (NP + 2) + t) * NP + b];
 #pragma unroll
     for (int s = 0; s < NP; ++s) {
       T acc = T(0);
@@ -170,75 +300,41 @@ __global__ __launch_bounds__(64) void k_dg_stage(
       nd[v][s] = acc;
     }
     T an = T(0), as = T(0), ae = T(0), aw = T(0);
+    T ne = T(0), nw = T(0), nn = T(0), ns = T(0);
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
       an += col[b] * gt->Pp[b];
       as += col[b] * gt->Pm[b];
-      ae += ce[b] * gt->B[t][b];
-      aw += cw[b] * gt->B[t][b];
+      ae += S[(v * (NP + 2) + NP) * NP + b] * bt[b];
+      aw += S[(v * (NP + 2) + NP + 1) * NP + b] * bt[b];
+      ne += S[NB + (0 * 3 + v) * NP + b] * bt[b];
+      nw += S[NB + (1 * 3 + v) * NP + b] * bt[b];
+      nn += S[NB + (2 * 3 + v) * NP + b] * bt[b];
+      ns += S[NB + (3 * 3 + v) * NP + b] * bt[b];
     }
     trN[v] = an; trS[v] = as; trE[v] = ae; trW[v] = aw;
+    nbE[v] = ne; nbW[v] = nw; nbN[v] = nn; nbS[v] = ns;
   }
-  __syncthreads();
-
-  // ---- neighbour traces at the shared edges
-  const bool hasN = j < n_lat - 1, hasS = j > 0;
-  const int eE = (i + 1 == n_lon) ? e + 1 - n_lon : e + 1;
-  const int eW = (i == 0) ? e - 1 + n_lon : e - 1;
-  const int eN = hasN ? e + n_lon : e;
-  const int eS = hasS ? e - n_lon : e;
-  {
-    const T *rE = q + (size_t)eE * 3 * N + t * NP;   // row b = t
-    const T *rW = q + (size_t)eW * 3 * N + t * NP;
-    const T *cN = q + (size_t)eN * 3 * N + t;        // column a = t
-    const T *cS = q + (size_t)eS * 3 * N + t;
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      T ue = T(0), uw = T(0), vn = T(0), vs = T(0);
-#pragma unroll
-      for (int k = 0; k < NP; ++k) {
-        T xe = rE[v * N + k], xw = rW[v * N + k];
-        T xn = cN[v * N + k * NP], xs = cS[v * N + k * NP];
-        if (v == 0 && t == 0 && k == 0) { xe -= H2; xw -= H2; xn -= H2; xs -= H2; }
-        ue += xe * gt->Pm[k];   // east neighbour seen from its west edge
-        uw += xw * gt->Pp[k];   // west neighbour seen from its east edge
-        vn += xn * gt->Pm[k];   // north neighbour seen from its south edge
-        vs += xs * gt->Pp[k];   // south neighbour seen from its north edge
-      }
-      S[(0 * 3 + v) * NP + t] = ue;
-      S[(1 * 3 + v) * NP + t] = uw;
-      S[(2 * 3 + v) * NP + t] = vn;
-      S[(3 * 3 + v) * NP + t] = vs;
-    }
-  }
-  __syncthreads();
-  T nbE[3], nbW[3], nbN[3], nbS[3];
-#pragma unroll
-  for (int v = 0; v < 3; ++v) {
-    T ae = T(0), aw = T(0), an = T(0), as = T(0);
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      const T bt = gt->B[t][k];
-      ae += S[(0 * 3 + v) * NP + k] * bt;
-      aw += S[(1 * 3 + v) * NP + k] * bt;
-      an += S[(2 * 3 + v) * NP + k] * bt;
-      as += S[(3 * 3 + v) * NP + k] * bt;
-    }
-    nbE[v] = ae; nbW[v] = aw; nbN[v] = an; nbS[v] = as;
-  }
-  __syncthreads();
+  wave_sync();
 
   // ---- Rusanov fluxes at edge node t of the four edges (minus = west/south)
   T FhE[3], FhW[3], GhN[3], GhS[3];
   rusanov_lambda<T>(trE, nbE, H, grav, fixed, alpha, FhE);
   rusanov_lambda<T>(nbW, trW, H, grav, fixed, alpha, FhW);
-  rusanov_theta<T>(trN, nbN, H, grav, fixed, alpha, GhN);
-  rusanov_theta<T>(nbS, trS, H, grav, fixed, alpha, GhS);
-  const T fN = hasN ? rt.ctop * invR : T(0);   // zero flux through a pole
-  const T fS = hasS ? rt.cbot * invR : T(0);
+  if (hasN) {
+    rusanov_theta<T>(trN, nbN, H, grav, fixed, alpha, GhN);
+  }
+  if (hasS) {
+    rusanov_theta<T>(nbS, trS, H, grav, fixed, alpha, GhS);
+  }
+  const T fN = hasN ? rt->ctop * invR : T(0);   // zero flux through a pole
+  const T fS = hasS ? rt->cbot * invR : T(0);
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
-    FhE[v] *= invR; FhW[v] *= invR; GhN[v] *= fN; GhS[v] *= fS;
+    FhE[v] *= invR;
+    FhW[v] *= invR;
+    GhN[v] = hasN ? GhN[v] * fN : T(0);
+    GhS[v] = hasS ? GhS[v] * fS : T(0);
   }
 
   // ---- volume: fluxes and sources at the nodes (p = t, s), contracted over s
@@ -256,10 +352,10 @@ __global__ __launch_bounds__(64) void k_dg_stage(
   for (int s = 0; s < NP; ++s) {
     const T dh = nd[0][s], hu = nd[1][s], hv = nd[2][s];
     const T h = dh + H;
-    const T rh = T(1) / h;
+    const T rh = dg_rcp(h);
     const T u = hu * rh, vv = hv * rh;
     const T pr = T(0.5) * grav * dh * (h + H);
-    const T c = rt.cosn[s], sn = rt.sinn[s], st = rt.stil[s];
+    const T c = rt->cosn[s], sn = rt->sinn[s], st = rt->stil[s];
     const T F0 = hu * invR, F1 = (hu * u + pr) * invR, F2 = hu * vv * invR;
     const T cR = c * invR;
     const T G0 = hv * cR, G1 = hv * u * cR, G2 = (hv * vv + pr) * cR;
@@ -267,18 +363,18 @@ __global__ __launch_bounds__(64) void k_dg_stage(
     const T S1 = C * hv, S2 = -pr * st * invR - C * hu;
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
-      const T bm = rt.BM[s][b], dm = rt.DM[s][b];
+      const T bm = rt->BM[s][b], dm = rt->DM[s][b];
       ZD[0][b] += F0 * bm; ZD[1][b] += F1 * bm; ZD[2][b] += F2 * bm;
       ZG[0][b] += G0 * dm; ZG[1][b] += G1 * dm; ZG[2][b] += G2 * dm;
       ZS[0][b] += S1 * bm; ZS[1][b] += S2 * bm;
     }
   }
-  const T wt = gt->w[t], cF = gt->cF, cG = gt->cG;
+  const T wt = tab[NP * NP + t], cF = gt->cF, cG = gt->cG;
 #pragma unroll
   for (int v = 0; v < 3; ++v)
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
-      const T zg = ZG[v][b] - (GhN[v] * rt.MN[b] - GhS[v] * rt.MS[b]);
+      const T zg = ZG[v][b] - (GhN[v] * rt->MN[b] - GhS[v] * rt->MS[b]);
       const T zs = v == 0 ? T(0) : ZS[v - 1][b];
       S[((v * 2 + 0) * NP + t) * NP + b] = cF * wt * ZD[v][b];
       S[((v * 2 + 1) * NP + t) * NP + b] = wt * (cG * zg + zs);
@@ -288,10 +384,33 @@ __global__ __launch_bounds__(64) void k_dg_stage(
     S[6 * NP * NP + (v * 2 + 0) * NP + t] = FhE[v];
     S[6 * NP * NP + (v * 2 + 1) * NP + t] = FhW[v];
   }
-  __syncthreads();
+  wave_sync();
+
+  // ---- the epilogue's operands, loaded late to keep registers free: q (again,
+  // from cache), q^n and the forcing
+  const bool use_q0 = combine && c0 != T(0);
+  T q0r[3][NP], fr[3][NP];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    if (combine) load_row<T, NP>(q + base + v * N, qr[v]);
+    if (use_q0) {
+      load_row<T, NP>(q0 + base + v * N, q0r[v]);
+    } else {
+#pragma unroll
+      for (int a = 0; a < NP; ++a) q0r[v][a] = T(0);
+    }
+    if (forcing) {
+      load_row<T, NP>(forcing + base + v * N, fr[v]);
+    } else {
+#pragma unroll
+      for (int a = 0; a < NP; ++a) fr[v][a] = T(0);
+    }
+  }
 
   // ---- xi pass back to modes: lane t = latitude degree b
-  const size_t base = (size_t)e * 3 * N + t * NP;
+  T bmt[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) bmt[p] = tab[NP * NP + NP + p * NP + t];   // BM[p][t]
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
     T zd[NP], zb[NP];
@@ -300,26 +419,20 @@ __global__ __launch_bounds__(64) void k_dg_stage(
     for (int p = 0; p < NP; ++p) {
       zd[p] = S[((v * 2 + 0) * NP + p) * NP + t];
       zb[p] = S[((v * 2 + 1) * NP + p) * NP + t];
-      const T bms = rt.BM[p][t];
-      XE += S[6 * NP * NP + (v * 2 + 0) * NP + p] * bms;
-      XW += S[6 * NP * NP + (v * 2 + 1) * NP + p] * bms;
+      XE += S[6 * NP * NP + (v * 2 + 0) * NP + p] * bmt[p];
+      XW += S[6 * NP * NP + (v * 2 + 1) * NP + p] * bmt[p];
     }
+    T res[NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
       T acc = T(0);
 #pragma unroll
       for (int p = 0; p < NP; ++p) acc += gt->D[p][a] * zd[p] + gt->B[p][a] * zb[p];
       acc -= cF * (gt->Pp[a] * XE - gt->Pm[a] * XW);
-      if (forcing) acc += forcing[base + v * N + a];
-      if (active) {
-        if (combine) {
-          const T qn = (c0 != T(0)) ? q0[base + v * N + a] : T(0);
-          out[base + v * N + a] = c0 * qn + c1 * (qr[v][a] + dt * acc);
-        } else {
-          out[base + v * N + a] = acc;
-        }
-      }
+      acc += fr[v][a];
+      res[a] = combine ? c0 * q0r[v][a] + c1 * (qr[v][a] + dt * acc) : acc;
     }
+    if (active) store_row<T, NP>(out + base + v * N, res);
   }
 }
 
@@ -384,12 +497,13 @@ __global__ __launch_bounds__(kMassThreads) void k_mass_final(const double *__res
 template <typename T, int NP>
 static hipError_t launch_stage_t(const StageLaunch &a, hipStream_t s) {
   constexpr int GPW = Shape<T, NP>::GPW;
-  const int grid = (a.E + GPW - 1) / GPW;
+  const int segs = (a.n_lon + GPW - 1) / GPW;
+  const int grid = segs * a.n_lat;
   hipLaunchKernelGGL((k_dg_stage<T, NP>), dim3(grid), dim3(64), 0, s,
                      static_cast<const T *>(a.q), static_cast<const T *>(a.q0),
                      static_cast<T *>(a.out), static_cast<const T *>(a.forcing),
                      static_cast<const GlobTab<T, NP> *>(a.glob),
-                     static_cast<const RowTab<T, NP> *>(a.rows), a.n_lon, a.n_lat, a.E,
+                     static_cast<const RowTab<T, NP> *>(a.rows), a.n_lon, a.n_lat, segs,
                      a.alpha_global, a.combine, T(a.c0), T(a.c1), T(a.dt));
   return hipGetLastError();
 }
