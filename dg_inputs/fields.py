@@ -116,3 +116,16 @@ def lake_at_rest_state(n_lon, n_lat, order, h0=1.0e4):
     q = np.zeros((n_lon * n_lat, 3, n * n))
     q[:, 0, 0] = 2.0 * h0
     return q
+
+
+def ensemble_members(n_members=64, seed=4, orders=(2, 3, 4), n_lats=(45, 90, 135, 180)):
+    """Uneven ensemble: order r and latitude count drawn uniformly by seed,
+    n_lon = 2 n_lat.  Returns a list of dicts (n_lon, n_lat, order, seed),
+    member k's fields seeded with seed * 1000 + k."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_members):
+        r = int(rng.choice(orders))
+        nt = int(rng.choice(n_lats))
+        out.append({"n_lon": 2 * nt, "n_lat": nt, "order": r, "seed": seed * 1000 + k})
+    return out

@@ -153,6 +153,64 @@ int dg_mass(dg_ctx *ctx, const void *q, double out[3], void *hip_stream);
  * it is set. */
 int dg_set_forcing(dg_ctx *ctx, const void *fhat);
 
+/* ---------------------------------------------------------------------------
+ * Ensembles: many independent meshes of different size and order advanced by
+ * one kernel launch per Runge-Kutta stage (a batch of independent problems, the
+ * generalisation of the paper's identical "vertical levels" of section 5.2 to
+ * members of uneven degree and resolution).  All members share the dtype.
+ * Member m's state occupies values [offsets[m], offsets[m] + state_m) of the
+ * packed buffer, state_m = E_m * 3 * N_m, offsets 16-byte aligned; the gaps
+ * between members are never read or written.
+ * ------------------------------------------------------------------------- */
+typedef struct dg_ens dg_ens;
+
+/* members: n_members >= 1 descriptors, same dtype.  Builds one context per
+ * member plus the work list of the persistent kernel.  *out NULL on failure. */
+int dg_ens_init(const dg_mesh_desc *members, int32_t n_members, void *hip_stream,
+                dg_ens **out);
+int dg_ens_free(dg_ens *ens);
+/* Values of one packed state buffer (dg_ens_rk_step's work needs twice this). */
+int dg_ens_state_size(const dg_ens *ens, int64_t *n_values);
+/* offsets[0..n_members] (host array of n_members + 1), in values. */
+int dg_ens_offsets(const dg_ens *ens, int64_t *offsets);
+/* The context of member m (owned by the ensemble; do not free), e.g. for
+ * dg_min_width or dg_mass on the member's slice of the packed state. */
+int dg_ens_member(dg_ens *ens, int32_t m, dg_ctx **ctx);
+/* Per-member time steps dt[0..n_members) [s], copied to the device
+ * (synchronously); used by every following stage or step, and by graphs
+ * replayed later. */
+int dg_ens_set_dt(dg_ens *ens, const double *dt);
+/* dqdt = M^-1 h(q) for every member (one launch); q and dqdt must not overlap. */
+int dg_ens_rhs(dg_ens *ens, const void *q, void *dqdt, void *hip_stream);
+/* One stage for all members: out = c0 q0 + c1 (q + dt_m L_m(q)); same aliasing
+ * rules as dg_rk_stage. */
+int dg_ens_rk_stage(dg_ens *ens, const void *q, const void *q0, void *out, double c0,
+                    double c1, void *hip_stream);
+/* nsteps SSP-RK3 steps of every member (3 launches per step); work = 2 packed
+ * states. */
+int dg_ens_rk_step(dg_ens *ens, void *q, void *work, int32_t nsteps, void *hip_stream);
+/* Schedule of the persistent kernel: wavefronts per workgroup (1, 2 or 4) and
+ * workgroups, each taking one contiguous, cost-balanced range of the work list. */
+int dg_ens_set_schedule(dg_ens *ens, int32_t waves_per_group, int32_t groups);
+int dg_ens_get_schedule(const dg_ens *ens, int32_t *waves_per_group, int32_t *groups);
+/* Pick the fastest schedule by timing stages on q (read only) and work (2
+ * packed states, overwritten); with cache_path, reuse or record the choice
+ * keyed by the device and the member list.  Synchronises hip_stream. */
+int dg_ens_autotune(dg_ens *ens, const void *q, void *work, const char *cache_path,
+                    void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * HIP graphs of whole step sequences (launch cost paid once per replay).
+ * The pointers and step sizes are baked in at capture (an ensemble's dt is
+ * read from its device table at run time, so dg_ens_set_dt still applies).
+ * ------------------------------------------------------------------------- */
+typedef struct dg_graph dg_graph;
+int dg_graph_rk(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme,
+                int32_t nsteps, dg_graph **out);
+int dg_graph_ens(dg_ens *ens, void *q, void *work, int32_t nsteps, dg_graph **out);
+int dg_graph_launch(dg_graph *graph, void *hip_stream);
+int dg_graph_free(dg_graph *graph);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char *dg_last_error(void);
 

@@ -12,7 +12,8 @@ from ._lib import (DG_ALPHA_GLOBAL, DG_ALPHA_LOCAL, DG_F32, DG_F64, DG_METRIC_BA
                    DG_METRIC_POINTWISE, DG_SSP_RK1, DG_SSP_RK2, DG_SSP_RK3, DGError,
                    MeshDesc, check, load)
 
-__all__ = ["Mesh", "DGError", "cfl_time_step", "DG_SSP_RK1", "DG_SSP_RK2", "DG_SSP_RK3"]
+__all__ = ["Mesh", "Ensemble", "Graph", "DGError", "cfl_time_step", "DG_SSP_RK1", "DG_SSP_RK2",
+           "DG_SSP_RK3"]
 
 RADIUS, GRAVITY, OMEGA = 6.371e6, 9.80616, 7.292e-5
 
@@ -29,33 +30,79 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def make_desc(n_lon, n_lat, order, dtype="f64", metric="balanced", alpha_mode="local",
+              alpha=0.0, radius=RADIUS, gravity=GRAVITY, omega=OMEGA, h_ref=0.0):
+    d = MeshDesc()
+    d.abi_version = 1
+    d.n_lon, d.n_lat, d.order = int(n_lon), int(n_lat), int(order)
+    d.dtype = {"f64": DG_F64, "f32": DG_F32}[_dtype_name(dtype)]
+    d.metric = {"balanced": DG_METRIC_BALANCED, "pointwise": DG_METRIC_POINTWISE}[metric]
+    d.alpha_mode = {"local": DG_ALPHA_LOCAL, "global": DG_ALPHA_GLOBAL}[alpha_mode]
+    d.reserved = 0
+    d.alpha, d.radius, d.gravity, d.omega, d.h_ref = alpha, radius, gravity, omega, h_ref
+    return d
+
+
+def _dtype_name(dtype):
+    if dtype in ("f64", "f32"):
+        return dtype
+    import torch
+    return {torch.float64: "f64", torch.float32: "f32"}[dtype]
+
+
+class Graph:
+    """A captured, instantiated sequence of steps; launch() replays it."""
+
+    def __init__(self, lib, handle, keep):
+        self._lib, self._g, self._keep = lib, handle, keep
+
+    def launch(self, stream=None):
+        check(self._lib.dg_graph_launch(self._g, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_g", None):
+            self._lib.dg_graph_free(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Mesh:
     """One mesh and basis: a dg_ctx of the C library."""
 
     def __init__(self, n_lon, n_lat, order, dtype="f64", metric="balanced",
                  alpha_mode="local", alpha=0.0, radius=RADIUS, gravity=GRAVITY,
                  omega=OMEGA, h_ref=0.0, stream=None):
-        import torch
         self._lib = load()
-        self.dtype = {"f64": torch.float64, "f32": torch.float32,
-                      torch.float64: torch.float64, torch.float32: torch.float32}[dtype]
-        d = MeshDesc()
-        d.abi_version = 1
-        d.n_lon, d.n_lat, d.order = int(n_lon), int(n_lat), int(order)
-        d.dtype = DG_F64 if self.dtype == torch.float64 else DG_F32
-        d.metric = {"balanced": DG_METRIC_BALANCED, "pointwise": DG_METRIC_POINTWISE}[metric]
-        d.alpha_mode = {"local": DG_ALPHA_LOCAL, "global": DG_ALPHA_GLOBAL}[alpha_mode]
-        d.reserved = 0
-        d.alpha, d.radius, d.gravity, d.omega, d.h_ref = alpha, radius, gravity, omega, h_ref
+        d = make_desc(n_lon, n_lat, order, dtype, metric, alpha_mode, alpha, radius, gravity,
+                      omega, h_ref)
+        ctx = ctypes.c_void_p()
+        check(self._lib.dg_init_mesh(ctypes.byref(d), _stream_handle(stream), ctypes.byref(ctx)))
+        self._setup(d, ctx, owns=True)
+
+    @classmethod
+    def _borrowed(cls, desc, ctx):
+        """A view of a context owned elsewhere (an ensemble member)."""
+        m = cls.__new__(cls)
+        m._lib = load()
+        m._setup(desc, ctx, owns=False)
+        return m
+
+    def _setup(self, d, ctx, owns):
+        import torch
         self.desc = d
+        self.dtype = torch.float64 if d.dtype == DG_F64 else torch.float32
         self.n_lon, self.n_lat, self.order = d.n_lon, d.n_lat, d.order
         self.n = self.order + 1
         self.N = self.n * self.n
         self.E = self.n_lon * self.n_lat
         self.shape = (self.E, 3, self.N)
-        ctx = ctypes.c_void_p()
-        check(self._lib.dg_init_mesh(ctypes.byref(d), _stream_handle(stream), ctypes.byref(ctx)))
         self._ctx = ctx
+        self._owns = owns
         self._forcing = None
 
     # -- sizes
@@ -131,10 +178,131 @@ class Mesh:
             check(self._lib.dg_set_forcing(self._ctx, self._ptr(fhat, "fhat")))
         self._forcing = fhat
 
+    def graph(self, q, work, dt, scheme=DG_SSP_RK3, nsteps=1):
+        """Capture nsteps steps on q/work as a HIP graph (pointers baked in)."""
+        g = ctypes.c_void_p()
+        check(self._lib.dg_graph_rk(self._ctx, self._ptr(q, "q"),
+                                    self._ptr(work, "work", self.work_size(scheme)), float(dt),
+                                    int(scheme), int(nsteps), ctypes.byref(g)))
+        return Graph(self._lib, g, (q, work))
+
     def close(self):
-        if getattr(self, "_ctx", None):
+        if getattr(self, "_ctx", None) and getattr(self, "_owns", False):
             self._lib.dg_free(self._ctx)
-            self._ctx = None
+        self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ensemble:
+    """Independent meshes of different size and order advanced together: one
+    persistent kernel launch per Runge-Kutta stage (dg_ens_* of the C ABI).
+
+    members: list of dicts with n_lon, n_lat, order (and optionally metric,
+    alpha_mode, alpha, h_ref).  The state is one packed tensor; views() gives
+    each member's (E, 3, N) slice."""
+
+    def __init__(self, members, dtype="f32", stream=None, **common):
+        self._lib = load()
+        descs = (MeshDesc * len(members))()
+        for k, m in enumerate(members):
+            kw = dict(common)
+            kw.update({key: v for key, v in m.items()
+                       if key in ("metric", "alpha_mode", "alpha", "h_ref", "radius", "gravity",
+                                  "omega")})
+            descs[k] = make_desc(m["n_lon"], m["n_lat"], m["order"], dtype, **kw)
+        e = ctypes.c_void_p()
+        check(self._lib.dg_ens_init(descs, len(members), _stream_handle(stream), ctypes.byref(e)))
+        self._e = e
+        self._descs = descs
+        self.n = len(members)
+        n = ctypes.c_int64()
+        check(self._lib.dg_ens_state_size(e, ctypes.byref(n)))
+        self.size = n.value
+        offs = (ctypes.c_int64 * (self.n + 1))()
+        check(self._lib.dg_ens_offsets(e, offs))
+        self.offsets = [offs[k] for k in range(self.n + 1)]
+        self.members = []
+        for k in range(self.n):
+            c = ctypes.c_void_p()
+            check(self._lib.dg_ens_member(e, k, ctypes.byref(c)))
+            self.members.append(Mesh._borrowed(descs[k], c))
+        self.dtype = self.members[0].dtype
+
+    def empty_state(self, device="cuda"):
+        import torch
+        return torch.zeros(self.size, dtype=self.dtype, device=device)
+
+    def empty_work(self, device="cuda"):
+        import torch
+        return torch.zeros(2 * self.size, dtype=self.dtype, device=device)
+
+    def views(self, q):
+        """Per-member (E, 3, N) views into a packed state."""
+        return [q[self.offsets[k]:self.offsets[k] + m.state_size()].view(m.shape)
+                for k, m in enumerate(self.members)]
+
+    def _ptr(self, t, name, numel):
+        if not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous() or t.numel() != numel:
+            raise ValueError(f"{name}: need a contiguous {self.dtype} GPU tensor of {numel} values")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_dt(self, dts):
+        arr = (ctypes.c_double * self.n)(*[float(x) for x in dts])
+        check(self._lib.dg_ens_set_dt(self._e, arr))
+
+    def rhs(self, q, out=None, stream=None):
+        if out is None:
+            out = self.empty_state(q.device)
+        check(self._lib.dg_ens_rhs(self._e, self._ptr(q, "q", self.size),
+                                   self._ptr(out, "out", self.size), _stream_handle(stream)))
+        return out
+
+    def rk_stage(self, q, q0, out, c0, c1, stream=None):
+        p0 = self._ptr(q0, "q0", self.size) if q0 is not None else None
+        check(self._lib.dg_ens_rk_stage(self._e, self._ptr(q, "q", self.size), p0,
+                                        self._ptr(out, "out", self.size), float(c0), float(c1),
+                                        _stream_handle(stream)))
+        return out
+
+    def rk_step(self, q, work, nsteps=1, stream=None):
+        check(self._lib.dg_ens_rk_step(self._e, self._ptr(q, "q", self.size),
+                                       self._ptr(work, "work", 2 * self.size), int(nsteps),
+                                       _stream_handle(stream)))
+        return q
+
+    def set_schedule(self, waves_per_group, groups):
+        check(self._lib.dg_ens_set_schedule(self._e, int(waves_per_group), int(groups)))
+
+    def schedule(self):
+        w, g = ctypes.c_int32(), ctypes.c_int32()
+        check(self._lib.dg_ens_get_schedule(self._e, ctypes.byref(w), ctypes.byref(g)))
+        return w.value, g.value
+
+    def autotune(self, q, work, cache_path=None, stream=None):
+        path = cache_path.encode() if cache_path else None
+        check(self._lib.dg_ens_autotune(self._e, self._ptr(q, "q", self.size),
+                                        self._ptr(work, "work", 2 * self.size), path,
+                                        _stream_handle(stream)))
+        return self.schedule()
+
+    def graph(self, q, work, nsteps=1):
+        g = ctypes.c_void_p()
+        check(self._lib.dg_graph_ens(self._e, self._ptr(q, "q", self.size),
+                                     self._ptr(work, "work", 2 * self.size), int(nsteps),
+                                     ctypes.byref(g)))
+        return Graph(self._lib, g, (q, work))
+
+    def close(self):
+        for m in getattr(self, "members", []):
+            m._ctx = None
+        if getattr(self, "_e", None):
+            self._lib.dg_ens_free(self._e)
+            self._e = None
 
     def __del__(self):
         try:

@@ -23,7 +23,11 @@ ERROR_NAMES = {
 
 # every symbol include/dgsw.h declares
 EXPORTS = ("dg_init_mesh", "dg_free", "dg_state_size", "dg_work_size", "dg_min_width", "dg_rhs",
-           "dg_rk_stage", "dg_rk_step", "dg_mass", "dg_set_forcing", "dg_last_error")
+           "dg_rk_stage", "dg_rk_step", "dg_mass", "dg_set_forcing", "dg_last_error",
+           "dg_ens_init", "dg_ens_free", "dg_ens_state_size", "dg_ens_offsets", "dg_ens_member",
+           "dg_ens_set_dt", "dg_ens_rhs", "dg_ens_rk_stage", "dg_ens_rk_step", "dg_ens_set_schedule",
+           "dg_ens_get_schedule", "dg_ens_autotune", "dg_graph_rk", "dg_graph_ens",
+           "dg_graph_launch", "dg_graph_free")
 
 
 class DGError(RuntimeError):
@@ -65,6 +69,24 @@ def load():
     lib.dg_rk_step.argtypes = [vp, vp, vp, ctypes.c_double, i32, i32, vp]
     lib.dg_mass.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.dg_set_forcing.argtypes = [vp, vp]
+    dp = ctypes.POINTER(ctypes.c_double)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.dg_ens_init.argtypes = [ctypes.POINTER(MeshDesc), i32, vp, ctypes.POINTER(vp)]
+    lib.dg_ens_free.argtypes = [vp]
+    lib.dg_ens_state_size.argtypes = [vp, i64p]
+    lib.dg_ens_offsets.argtypes = [vp, i64p]
+    lib.dg_ens_member.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    lib.dg_ens_set_dt.argtypes = [vp, dp]
+    lib.dg_ens_rhs.argtypes = [vp, vp, vp, vp]
+    lib.dg_ens_rk_stage.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp]
+    lib.dg_ens_rk_step.argtypes = [vp, vp, vp, i32, vp]
+    lib.dg_ens_set_schedule.argtypes = [vp, i32, i32]
+    lib.dg_ens_get_schedule.argtypes = [vp, i32p, i32p]
+    lib.dg_ens_autotune.argtypes = [vp, vp, vp, ctypes.c_char_p, vp]
+    lib.dg_graph_rk.argtypes = [vp, vp, vp, ctypes.c_double, i32, i32, ctypes.POINTER(vp)]
+    lib.dg_graph_ens.argtypes = [vp, vp, vp, i32, ctypes.POINTER(vp)]
+    lib.dg_graph_launch.argtypes = [vp, vp]
+    lib.dg_graph_free.argtypes = [vp]
     lib.dg_last_error.argtypes = []
     lib.dg_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:

@@ -10,26 +10,13 @@
 #include <string>
 #include <vector>
 
+#include "dgsw_ctx.hpp"
 #include "dgsw_device.hpp"
 #include "dgsw_tables.hpp"
 
-struct dg_ctx {
-  dg_mesh_desc d;
-  int np = 0, N = 0, E = 0;
-  int64_t state_n = 0;
-  size_t elem_bytes = 0;
-  void *d_glob = nullptr;
-  void *d_rows = nullptr;
-  double *d_mass_w = nullptr;
-  double *d_partial = nullptr;
-  double *d_out4 = nullptr;
-  const void *forcing = nullptr;
-  double min_width = 0.0;
-};
+namespace dgsw {
 
-namespace {
-
-thread_local std::string g_err;
+static thread_local std::string g_err;
 
 int fail(int code, const std::string &msg) {
   g_err = msg;
@@ -41,6 +28,16 @@ int hip_fail(hipError_t e, const char *what) {
 }
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+const char *last_error() { return g_err.c_str(); }
+
+}  // namespace dgsw
+
+using dgsw::aligned16;
+using dgsw::fail;
+using dgsw::hip_fail;
+
+namespace {
 
 void release(dg_ctx *c) {
   if (!c) return;
@@ -82,7 +79,7 @@ int validate(const dg_mesh_desc *d) {
 
 extern "C" {
 
-const char *dg_last_error(void) { return g_err.c_str(); }
+const char *dg_last_error(void) { return dgsw::last_error(); }
 
 int dg_init_mesh(const dg_mesh_desc *desc, void *hip_stream, dg_ctx **out) {
   if (!out) return fail(DG_EINVAL, "out is NULL");

@@ -1,0 +1,29 @@
+// Context of one mesh and the error helpers shared by the C ABI sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "dgsw.h"
+
+struct dg_ctx {
+  dg_mesh_desc d;
+  int np = 0, N = 0, E = 0;
+  int64_t state_n = 0;
+  size_t elem_bytes = 0;
+  void *d_glob = nullptr;      // GlobTab<T, np>
+  void *d_rows = nullptr;      // RowTab<T, np>[n_lat]
+  double *d_mass_w = nullptr;  // mass diagnostic weights [n_lat][np]
+  double *d_partial = nullptr; // mass partial sums
+  double *d_out4 = nullptr;    // mass result
+  const void *forcing = nullptr;
+  double min_width = 0.0;
+};
+
+namespace dgsw {
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+bool aligned16(const void *p);
+}  // namespace dgsw

@@ -172,23 +172,36 @@ __device__ __forceinline__ void rusanov_theta(const T qm[3], const T qp[3], T H,
   out[2] = T(0.5) * ((qm[2] * m.v + m.p) + (qp[2] * p.v + p.p)) - T(0.5) * a * (qp[2] - qm[2]);
 }
 
-// Wavefront = GPW elements of one latitude row (segment `seg` of row j), so
-// the row's tables are wave-uniform (scalar loads) and the pole tests are
-// uniform branches.  Grid = n_lat * segs workgroups of 64 lanes.
+// Arguments of one stage on one mesh.
 template <typename T, int NP>
-__global__ __launch_bounds__(64) void k_dg_stage(
-    const T *__restrict__ q, const T *q0, T *out, const T *__restrict__ forcing,
-    const GlobTab<T, NP> *__restrict__ gt, const RowTab<T, NP> *__restrict__ rows,
-    int n_lon, int n_lat, int segs, int alpha_global, int combine, T c0, T c1, T dt) {
+struct StageArgs {
+  const T *q;            // state L is evaluated on
+  const T *q0;           // q^n of the combination (may alias out)
+  T *out;
+  const T *forcing;      // optional modal forcing
+  const GlobTab<T, NP> *gt;
+  const RowTab<T, NP> *rows;
+  int n_lon, n_lat, alpha_global, combine;
+  T c0, c1, dt;
+};
+
+// One wavefront's share of a stage: GPW elements of one latitude row
+// (segment `seg` of row j), so the row's tables are wave-uniform (scalar
+// loads) and the pole tests are uniform branches.  tab and sh are this
+// wavefront's LDS slices (TB and (GPW+1)*SH values).
+template <typename T, int NP>
+__device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int j, const int seg,
+                                           const int lane, T *tab, T *sh) {
   using S_ = Shape<T, NP>;
   constexpr int N = S_::N, GPW = S_::GPW, SH = S_::SH, NB = S_::NB, TB = S_::TB;
-  __shared__ T tab[TB];
-  __shared__ T sh[(GPW + 1) * SH];
-
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int j = blk / segs;
-  const int seg = blk - j * segs;
-  const int lane = threadIdx.x;
+  const T *__restrict__ q = A.q;
+  const T *q0 = A.q0;
+  T *out = A.out;
+  const T *__restrict__ forcing = A.forcing;
+  const GlobTab<T, NP> *__restrict__ gt = A.gt;
+  const RowTab<T, NP> *__restrict__ rows = A.rows;
+  const int n_lon = A.n_lon, n_lat = A.n_lat, combine = A.combine;
+  const T c0 = A.c0, c1 = A.c1, dt = A.dt;
   int g = lane / NP, t = lane - g * NP;
   const bool idle = g >= GPW;          // the 64 mod NP spare lanes: a dummy LDS slot
   if (idle) { g = GPW; t = lane - GPW * NP; }
@@ -200,7 +213,7 @@ __global__ __launch_bounds__(64) void k_dg_stage(
   const RowTab<T, NP> *rt = rows + j;
   const bool hasN = j < n_lat - 1, hasS = j > 0;
   const T H = gt->href, H2 = gt->two_href, grav = gt->g, invR = gt->invR;
-  const bool fixed = alpha_global != 0;
+  const bool fixed = A.alpha_global != 0;
   const T alpha = gt->alpha;
 
   // ---- every global load of the stage, issued up front
@@ -436,11 +449,121 @@ __global__ __launch_bounds__(64) void k_dg_stage(
   }
 }
 
+template <typename T, int NP, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_dg_stage(StageArgs<T, NP> A, int segs) {
+  using S_ = Shape<T, NP>;
+  // WPB independent wavefronts per workgroup (fewer workgroups to dispatch on
+  // large meshes); each wavefront has its own LDS slice and never waits for
+  // another one
+  __shared__ T tab_all[WPB][S_::TB];
+  __shared__ T sh_all[WPB][(S_::GPW + 1) * S_::SH];
+  const int wv = threadIdx.x >> 6;
+  const int blk = xcd_block(blockIdx.x, gridDim.x) * WPB + wv;
+  if (blk >= segs * A.n_lat) return;      // spare wavefront of the last workgroup
+  const int j = blk / segs;
+  stage_wave<T, NP>(A, j, blk - j * segs, threadIdx.x & 63, tab_all[wv], sh_all[wv]);
+}
+
+// ------------------------------------------------------------------ ensemble
+// LDS of one wavefront for any order up to NPMAX
+constexpr int lds_tab(int k) { return 2 * k * k + k; }
+constexpr int lds_sh(int k) {
+  return (64 / k + 1) * ((3 * (k + 2) * k + 12 * k) > (6 * k * k + 6 * k) ? (3 * (k + 2) * k + 12 * k)
+                                                                           : (6 * k * k + 6 * k));
+}
+constexpr int lds_max_tab(int npmax) { return npmax == 0 ? 0 : (lds_tab(npmax) > lds_max_tab(npmax - 1) ? lds_tab(npmax) : lds_max_tab(npmax - 1)); }
+constexpr int lds_max_sh(int npmax) { return npmax == 0 ? 0 : (lds_sh(npmax) > lds_max_sh(npmax - 1) ? lds_sh(npmax) : lds_max_sh(npmax - 1)); }
+
+template <typename T, int NP>
+__device__ __forceinline__ void ens_case(const EnsMember &m, const T *q, const T *q0, T *out,
+                                         int combine, T c0, T c1, int w, int lane, T *tab, T *sh) {
+  StageArgs<T, NP> A;
+  A.q = q + m.off;
+  A.q0 = q0 ? q0 + m.off : nullptr;
+  A.out = out + m.off;
+  A.forcing = nullptr;
+  A.gt = static_cast<const GlobTab<T, NP> *>(m.glob);
+  A.rows = static_cast<const RowTab<T, NP> *>(m.rows);
+  A.n_lon = m.n_lon;
+  A.n_lat = m.n_lat;
+  A.alpha_global = m.alpha_global;
+  A.combine = combine;
+  A.c0 = c0;
+  A.c1 = c1;
+  A.dt = T(m.dt);
+  const int j = w / m.segs;
+  stage_wave<T, NP>(A, j, w - j * m.segs, lane, tab, sh);
+}
+
+// One launch per Runge-Kutta stage for a whole ensemble of meshes of different
+// size and order, packed back to back in q / q0 / out.  Work unit: one
+// wavefront of one member (items[k] = {member, wave index}).  Workgroup b
+// (renumbered so each XCD gets a contiguous range) works through the
+// contiguous item range [bounds[b], bounds[b+1]), balanced by cost on the host;
+// its WPB wavefronts take every WPB-th item.  The order of each member is a
+// wave-uniform switch.
+template <typename T, int NPMAX, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_ens_stage(const T *__restrict__ q, const T *q0, T *out,
+                                                        const EnsMember *__restrict__ mem,
+                                                        const int2 *__restrict__ items,
+                                                        const int *__restrict__ bounds, int combine,
+                                                        T c0, T c1) {
+  __shared__ T tab_all[WPB][lds_max_tab(NPMAX)];
+  __shared__ T sh_all[WPB][lds_max_sh(NPMAX)];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  T *tab = tab_all[wv], *sh = sh_all[wv];
+  const int part = xcd_block(blockIdx.x, gridDim.x);
+  const int end = bounds[part + 1];
+  for (int it = bounds[part] + wv; it < end; it += WPB) {
+    const int2 w = items[it];
+    const EnsMember m = mem[w.x];
+    switch (m.np) {
+      case 1: ens_case<T, 1>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
+      case 2: ens_case<T, 2>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
+      case 3: ens_case<T, 3>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
+      case 4: ens_case<T, 4>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
+      case 5: ens_case<T, 5>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
+      default:
+        if constexpr (NPMAX > 5) {
+          switch (m.np) {
+            case 6: ens_case<T, (NPMAX > 5 ? 6 : 1)>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
+            case 7: ens_case<T, (NPMAX > 6 ? 7 : 1)>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
+            case 8: ens_case<T, (NPMAX > 7 ? 8 : 1)>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
+            default: break;
+          }
+        }
+        break;
+    }
+  }
+}
+
+template <typename T, int NPMAX, int WPB>
+static hipError_t launch_ens_t(const EnsLaunch &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_ens_stage<T, NPMAX, WPB>), dim3(a.parts), dim3(64 * WPB), 0, s,
+                     static_cast<const T *>(a.q), static_cast<const T *>(a.q0),
+                     static_cast<T *>(a.out), a.mem, a.items, a.bounds, a.combine, T(a.c0), T(a.c1));
+  return hipGetLastError();
+}
+
+hipError_t launch_ens_stage(int dtype, int npmax, int wpb, const EnsLaunch &a, hipStream_t s) {
+#define DGSW_ENS(NPM, W)                                                                  \
+  if (npmax <= NPM && wpb == W)                                                           \
+    return dtype == 0 ? launch_ens_t<double, NPM, W>(a, s) : launch_ens_t<float, NPM, W>(a, s);
+  DGSW_ENS(5, 1) DGSW_ENS(5, 2) DGSW_ENS(5, 4) DGSW_ENS(8, 1) DGSW_ENS(8, 2) DGSW_ENS(8, 4)
+#undef DGSW_ENS
+  return hipErrorInvalidValue;
+}
+
 // ------------------------------------------------------------------ mass
 constexpr int kMassThreads = 256;
 constexpr int kMassBlocks = 512;
 
 int mass_blocks() { return kMassBlocks; }
+
+int waves_per_row(int np, int n_lon) {
+  const int gpw = 64 / np;
+  return (n_lon + gpw - 1) / gpw;
+}
 
 template <int NT>
 __device__ __forceinline__ void block_sum4(double v[4], double *sh) {
@@ -495,16 +618,34 @@ __global__ __launch_bounds__(kMassThreads) void k_mass_final(const double *__res
 
 // ------------------------------------------------------------------ dispatch
 template <typename T, int NP>
+static StageArgs<T, NP> stage_args(const StageLaunch &a) {
+  StageArgs<T, NP> A;
+  A.q = static_cast<const T *>(a.q);
+  A.q0 = static_cast<const T *>(a.q0);
+  A.out = static_cast<T *>(a.out);
+  A.forcing = static_cast<const T *>(a.forcing);
+  A.gt = static_cast<const GlobTab<T, NP> *>(a.glob);
+  A.rows = static_cast<const RowTab<T, NP> *>(a.rows);
+  A.n_lon = a.n_lon;
+  A.n_lat = a.n_lat;
+  A.alpha_global = a.alpha_global;
+  A.combine = a.combine;
+  A.c0 = T(a.c0);
+  A.c1 = T(a.c1);
+  A.dt = T(a.dt);
+  return A;
+}
+
+template <typename T, int NP>
 static hipError_t launch_stage_t(const StageLaunch &a, hipStream_t s) {
   constexpr int GPW = Shape<T, NP>::GPW;
   const int segs = (a.n_lon + GPW - 1) / GPW;
-  const int grid = segs * a.n_lat;
-  hipLaunchKernelGGL((k_dg_stage<T, NP>), dim3(grid), dim3(64), 0, s,
-                     static_cast<const T *>(a.q), static_cast<const T *>(a.q0),
-                     static_cast<T *>(a.out), static_cast<const T *>(a.forcing),
-                     static_cast<const GlobTab<T, NP> *>(a.glob),
-                     static_cast<const RowTab<T, NP> *>(a.rows), a.n_lon, a.n_lat, segs,
-                     a.alpha_global, a.combine, T(a.c0), T(a.c1), T(a.dt));
+  const int waves = segs * a.n_lat;
+  const StageArgs<T, NP> A = stage_args<T, NP>(a);
+  if (waves >= 4096)
+    hipLaunchKernelGGL((k_dg_stage<T, NP, 4>), dim3((waves + 3) / 4), dim3(256), 0, s, A, segs);
+  else
+    hipLaunchKernelGGL((k_dg_stage<T, NP, 1>), dim3(waves), dim3(64), 0, s, A, segs);
   return hipGetLastError();
 }
 
