@@ -189,10 +189,15 @@ int dg_ens_rk_stage(dg_ens *ens, const void *q, const void *q0, void *out, doubl
 /* nsteps SSP-RK3 steps of every member (3 launches per step); work = 2 packed
  * states. */
 int dg_ens_rk_step(dg_ens *ens, void *q, void *work, int32_t nsteps, void *hip_stream);
-/* Schedule of the persistent kernel: wavefronts per workgroup (1, 2 or 4) and
- * workgroups, each taking one contiguous, cost-balanced range of the work list. */
-int dg_ens_set_schedule(dg_ens *ens, int32_t waves_per_group, int32_t groups);
-int dg_ens_get_schedule(const dg_ens *ens, int32_t *waves_per_group, int32_t *groups);
+/* Schedule of the persistent kernels: wavefronts per workgroup (1, 2 or 4),
+ * workgroups in total (each takes one contiguous, cost-balanced range of the
+ * work list, sorted by order; 0 = one workgroup per waves_per_group items, the
+ * default), and fused = 1 for a single launch covering all
+ * orders (its register budget is that of the union of the orders) or 0 for one
+ * launch per distinct order (each compiled for that order alone). */
+int dg_ens_set_schedule(dg_ens *ens, int32_t waves_per_group, int32_t groups, int32_t fused);
+int dg_ens_get_schedule(const dg_ens *ens, int32_t *waves_per_group, int32_t *groups,
+                        int32_t *fused);
 /* Pick the fastest schedule by timing stages on q (read only) and work (2
  * packed states, overwritten); with cache_path, reuse or record the choice
  * keyed by the device and the member list.  Synchronises hip_stream. */

@@ -275,13 +275,16 @@ class Ensemble:
                                        _stream_handle(stream)))
         return q
 
-    def set_schedule(self, waves_per_group, groups):
-        check(self._lib.dg_ens_set_schedule(self._e, int(waves_per_group), int(groups)))
+    def set_schedule(self, waves_per_group, groups, fused=False):
+        check(self._lib.dg_ens_set_schedule(self._e, int(waves_per_group), int(groups),
+                                            int(bool(fused))))
 
     def schedule(self):
-        w, g = ctypes.c_int32(), ctypes.c_int32()
-        check(self._lib.dg_ens_get_schedule(self._e, ctypes.byref(w), ctypes.byref(g)))
-        return w.value, g.value
+        """(waves per workgroup, workgroups, fused)."""
+        w, g, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(self._lib.dg_ens_get_schedule(self._e, ctypes.byref(w), ctypes.byref(g),
+                                            ctypes.byref(f)))
+        return w.value, g.value, bool(f.value)
 
     def autotune(self, q, work, cache_path=None, stream=None):
         path = cache_path.encode() if cache_path else None

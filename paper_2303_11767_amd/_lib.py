@@ -80,8 +80,8 @@ def load():
     lib.dg_ens_rhs.argtypes = [vp, vp, vp, vp]
     lib.dg_ens_rk_stage.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp]
     lib.dg_ens_rk_step.argtypes = [vp, vp, vp, i32, vp]
-    lib.dg_ens_set_schedule.argtypes = [vp, i32, i32]
-    lib.dg_ens_get_schedule.argtypes = [vp, i32p, i32p]
+    lib.dg_ens_set_schedule.argtypes = [vp, i32, i32, i32]
+    lib.dg_ens_get_schedule.argtypes = [vp, i32p, i32p, i32p]
     lib.dg_ens_autotune.argtypes = [vp, vp, vp, ctypes.c_char_p, vp]
     lib.dg_graph_rk.argtypes = [vp, vp, vp, ctypes.c_double, i32, i32, ctypes.POINTER(vp)]
     lib.dg_graph_ens.argtypes = [vp, vp, vp, i32, ctypes.POINTER(vp)]

@@ -58,27 +58,33 @@ struct StageLaunch {
 // dtype 0 = double, 1 = float; np = order + 1.  Returns a hipError_t.
 hipError_t launch_stage(int dtype, int np, const StageLaunch &a, hipStream_t s);
 
-// One ensemble member as the persistent ensemble kernel sees it.
-struct EnsMember {
+// One work item of the ensemble kernels: one wavefront of one member, with
+// everything the wavefront needs (a single 64-byte scalar load).
+struct alignas(16) EnsItem {
   const void *glob;   // GlobTab<T, np>
   const void *rows;   // RowTab<T, np>[n_lat]
   long long off;      // offset of the member's state in the packed buffers (values)
-  int n_lon, n_lat, np, segs, alpha_global, pad;
   double dt;
+  int n_lon, n_lat, np, j;
+  int seg, alpha_global, member, pad;
 };
 
 struct EnsLaunch {
   const void *q, *q0;
   void *out;
-  const EnsMember *mem;
-  const int2 *items;    // {member, wave index within the member}
+  const EnsItem *items;
   const int *bounds;    // parts + 1 item offsets, one contiguous range per workgroup
   int parts, combine;
+  int flat;             // one item per wavefront over [begin, end) (per-order launches)
+  int begin, end;
   double c0, c1;
 };
 
-// Ensemble stage: npmax = largest member order + 1 (<= 8), wpb in {1, 2, 4}.
+// Ensemble stage, all orders in one launch: npmax = largest member order + 1
+// (<= 8), wpb in {1, 2, 4}.
 hipError_t launch_ens_stage(int dtype, int npmax, int wpb, const EnsLaunch &a, hipStream_t s);
+// Ensemble stage over the members of one order np (items and bounds of that order).
+hipError_t launch_ens_stage_np(int dtype, int np, int wpb, const EnsLaunch &a, hipStream_t s);
 
 // Wavefronts (work items) of one member, and elements per wavefront.
 int waves_per_row(int np, int n_lon);

@@ -24,14 +24,16 @@ struct dg_ens {
   size_t elem_bytes = 0;
   std::vector<dg_ctx *> members;
   std::vector<int64_t> off;              // n + 1 packed offsets (values)
-  std::vector<dgsw::EnsMember> hmem;
-  std::vector<int2> items;               // {member, wave}
+  std::vector<dgsw::EnsItem> items;      // one wavefront of one member each
   std::vector<double> cost;              // per item
-  dgsw::EnsMember *d_mem = nullptr;
-  int2 *d_items = nullptr;
+  std::vector<double> dt;                // per member
+  dgsw::EnsItem *d_items = nullptr;
   int *d_bounds = nullptr;
   int bounds_cap = 0;
-  int wpb = 4, parts = 0;
+  int wpb = 4, parts = 0, fused = 0, flat = 1;
+  // members of one order form one contiguous group of the sorted work list
+  struct Group { int np, begin, end, parts, bounds_off; double cost; };
+  std::vector<Group> groups;
 };
 
 struct dg_graph {
@@ -44,38 +46,67 @@ namespace {
 void ens_release(dg_ens *e) {
   if (!e) return;
   for (dg_ctx *c : e->members) dg_free(c);
-  if (e->d_mem) (void)hipFree(e->d_mem);
   if (e->d_items) (void)hipFree(e->d_items);
   if (e->d_bounds) (void)hipFree(e->d_bounds);
   delete e;
 }
 
-// Contiguous cost-balanced ranges of the work list, one per workgroup.
-int upload_schedule(dg_ens *e, int wpb, int parts) {
-  const int n_items = (int)e->items.size();
-  if (parts < 1) parts = 1;
+// Split items [begin, end) into `parts` contiguous ranges of about equal cost;
+// appends parts + 1 absolute item offsets to b.
+void balanced_ranges(const dg_ens *e, int begin, int end, int parts, std::vector<int> &b) {
   double total = 0.0;
-  for (double c : e->cost) total += c;
-  std::vector<int> b(parts + 1, n_items);
-  b[0] = 0;
+  for (int it = begin; it < end; ++it) total += e->cost[it];
+  const size_t b0 = b.size();
+  b.push_back(begin);
   double acc = 0.0;
   int k = 1;
-  for (int it = 0; it < n_items && k < parts; ++it) {
+  for (int it = begin; it < end && k < parts; ++it) {
     acc += e->cost[it];
-    while (k < parts && acc >= total * k / parts) b[k++] = it + 1;
+    while (k < parts && acc >= total * k / parts) {
+      b.push_back(it + 1);
+      ++k;
+    }
   }
-  for (int p = 1; p <= parts; ++p) b[p] = std::max(b[p], b[p - 1]);
-  if (parts + 1 > e->bounds_cap) {
+  while ((int)(b.size() - b0) < parts + 1) b.push_back(end);
+}
+
+// Schedule: `parts` workgroups in total, each taking one contiguous,
+// cost-balanced range of the work list.  fused: one launch over all orders;
+// otherwise one launch per order with the workgroups shared out by cost.
+int upload_schedule(dg_ens *e, int wpb, int parts, int fused) {
+  // parts == 0: "flat", one workgroup per wpb consecutive items, scheduled by
+  // the hardware like an ordinary grid
+  const bool flat = parts == 0;
+  std::vector<int> b;
+  if (fused) {
+    const int n = (int)e->items.size();
+    const int p = flat ? (n + wpb - 1) / wpb : parts;
+    balanced_ranges(e, 0, n, p, b);
+  } else {
+    double total = 0.0;
+    for (const auto &g : e->groups) total += g.cost;
+    for (auto &g : e->groups) {
+      g.parts = flat ? (g.end - g.begin + wpb - 1) / wpb
+                     : std::max(1, (int)std::llround(parts * g.cost / total));
+      g.bounds_off = (int)b.size();
+      balanced_ranges(e, g.begin, g.end, g.parts, b);
+    }
+  }
+  if (fused && flat) parts = (int)b.size() - 1;
+  if ((int)b.size() > e->bounds_cap) {
     if (e->d_bounds) (void)hipFree(e->d_bounds);
     e->d_bounds = nullptr;
-    hipError_t err = hipMalloc(reinterpret_cast<void **>(&e->d_bounds), (parts + 1) * sizeof(int));
+    e->bounds_cap = 0;
+    hipError_t err = hipMalloc(reinterpret_cast<void **>(&e->d_bounds), b.size() * sizeof(int));
     if (err != hipSuccess) return fail(DG_ENOMEM, "hipMalloc of ensemble schedule");
-    e->bounds_cap = parts + 1;
+    e->bounds_cap = (int)b.size();
   }
-  hipError_t err = hipMemcpy(e->d_bounds, b.data(), (parts + 1) * sizeof(int), hipMemcpyHostToDevice);
+  hipError_t err = hipMemcpy(e->d_bounds, b.data(), b.size() * sizeof(int), hipMemcpyHostToDevice);
   if (err != hipSuccess) return hip_fail(err, "upload of ensemble schedule");
   e->wpb = wpb;
   e->parts = parts;
+  e->fused = fused;
+  e->flat = flat ? 1 : 0;
   return DG_OK;
 }
 
@@ -85,15 +116,28 @@ int ens_stage(dg_ens *e, const void *q, const void *q0, void *out, int combine, 
   a.q = q;
   a.q0 = q0;
   a.out = out;
-  a.mem = e->d_mem;
   a.items = e->d_items;
-  a.bounds = e->d_bounds;
-  a.parts = e->parts;
   a.combine = combine;
   a.c0 = c0;
   a.c1 = c1;
-  hipError_t err = dgsw::launch_ens_stage(e->dtype, e->npmax, e->wpb, a, s);
-  if (err != hipSuccess) return hip_fail(err, "ensemble stage launch");
+  a.flat = 0;
+  a.begin = a.end = 0;
+  if (e->fused) {
+    a.bounds = e->d_bounds;
+    a.parts = e->parts;
+    hipError_t err = dgsw::launch_ens_stage(e->dtype, e->npmax, e->wpb, a, s);
+    if (err != hipSuccess) return hip_fail(err, "ensemble stage launch");
+    return DG_OK;
+  }
+  for (const auto &g : e->groups) {
+    a.bounds = e->d_bounds + g.bounds_off;
+    a.parts = g.parts;
+    a.flat = e->flat;
+    a.begin = g.begin;
+    a.end = g.end;
+    hipError_t err = dgsw::launch_ens_stage_np(e->dtype, g.np, e->wpb, a, s);
+    if (err != hipSuccess) return hip_fail(err, "ensemble stage launch");
+  }
   return DG_OK;
 }
 
@@ -141,24 +185,49 @@ int dg_ens_init(const dg_mesh_desc *members, int32_t n_members, void *hip_stream
     e->members.push_back(c);
     e->npmax = std::max(e->npmax, c->np);
     e->off[m + 1] = e->off[m] + (c->state_n + align - 1) / align * align;
-    dgsw::EnsMember hm;
-    std::memset(&hm, 0, sizeof(hm));
-    hm.glob = c->d_glob;
-    hm.rows = c->d_rows;
-    hm.off = e->off[m];
-    hm.n_lon = c->d.n_lon;
-    hm.n_lat = c->d.n_lat;
-    hm.np = c->np;
-    hm.segs = dgsw::waves_per_row(c->np, c->d.n_lon);
-    hm.alpha_global = c->d.alpha_mode == DG_ALPHA_GLOBAL;
-    hm.dt = 0.0;
-    e->hmem.push_back(hm);
-    // work items of this member in row-major wave order; cost ~ lanes busy x work per lane
-    const int waves = hm.segs * hm.n_lat;
+    // work items of this member in row-major wave order; cost ~ work per wavefront
+    const int segs = dgsw::waves_per_row(c->np, c->d.n_lon);
     const double cost = (double)c->np * c->np * c->np;
-    for (int w = 0; w < waves; ++w) {
-      e->items.push_back(make_int2(m, w));
-      e->cost.push_back(cost);
+    for (int j = 0; j < c->d.n_lat; ++j)
+      for (int sg = 0; sg < segs; ++sg) {
+        dgsw::EnsItem it;
+        std::memset(&it, 0, sizeof(it));
+        it.glob = c->d_glob;
+        it.rows = c->d_rows;
+        it.off = e->off[m];
+        it.dt = 0.0;
+        it.n_lon = c->d.n_lon;
+        it.n_lat = c->d.n_lat;
+        it.np = c->np;
+        it.j = j;
+        it.seg = sg;
+        it.alpha_global = c->d.alpha_mode == DG_ALPHA_GLOBAL;
+        it.member = m;
+        e->items.push_back(it);
+        e->cost.push_back(cost);
+      }
+  }
+  e->dt.assign(n_members, 0.0);
+  {
+    // sort the work list by order (stable: members and rows keep their order)
+    std::vector<int> idx(e->items.size());
+    for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](int x, int y) { return e->items[x].np < e->items[y].np; });
+    std::vector<dgsw::EnsItem> it2(idx.size());
+    std::vector<double> c2(idx.size());
+    for (size_t k = 0; k < idx.size(); ++k) {
+      it2[k] = e->items[idx[k]];
+      c2[k] = e->cost[idx[k]];
+    }
+    e->items.swap(it2);
+    e->cost.swap(c2);
+    for (int k = 0; k < (int)e->items.size();) {
+      const int np = e->items[k].np;
+      dg_ens::Group g{np, k, k, 0, 0, 0.0};
+      while (k < (int)e->items.size() && e->items[k].np == np) g.cost += e->cost[k++];
+      g.end = k;
+      e->groups.push_back(g);
     }
   }
   if (e->off[n_members] >= (int64_t(1) << 31)) {
@@ -166,20 +235,16 @@ int dg_ens_init(const dg_mesh_desc *members, int32_t n_members, void *hip_stream
     return fail(DG_EINVAL, "packed ensemble state exceeds 2^31 values");
   }
   hipError_t err;
-  if ((err = hipMalloc(reinterpret_cast<void **>(&e->d_mem), n_members * sizeof(dgsw::EnsMember))) != hipSuccess ||
-      (err = hipMalloc(reinterpret_cast<void **>(&e->d_items), e->items.size() * sizeof(int2))) != hipSuccess) {
+  if ((err = hipMalloc(reinterpret_cast<void **>(&e->d_items), e->items.size() * sizeof(dgsw::EnsItem))) != hipSuccess) {
     ens_release(e);
     return fail(DG_ENOMEM, "hipMalloc of the ensemble work list");
   }
-  if ((err = hipMemcpy(e->d_mem, e->hmem.data(), n_members * sizeof(dgsw::EnsMember),
-                       hipMemcpyHostToDevice)) != hipSuccess ||
-      (err = hipMemcpy(e->d_items, e->items.data(), e->items.size() * sizeof(int2),
+  if ((err = hipMemcpy(e->d_items, e->items.data(), e->items.size() * sizeof(dgsw::EnsItem),
                        hipMemcpyHostToDevice)) != hipSuccess) {
     ens_release(e);
     return hip_fail(err, "upload of the ensemble work list");
   }
-  const int default_parts = std::max(1, std::min((int)e->items.size() / 4, 2048));
-  int rc = upload_schedule(e, 4, default_parts);
+  int rc = upload_schedule(e, 4, 0, 0);
   if (rc != DG_OK) {
     ens_release(e);
     return rc;
@@ -214,11 +279,11 @@ int dg_ens_member(dg_ens *ens, int32_t m, dg_ctx **ctx) {
 
 int dg_ens_set_dt(dg_ens *ens, const double *dt) {
   if (!ens || !dt) return fail(DG_EINVAL, "NULL argument");
-  for (int m = 0; m < ens->n; ++m) {
+  for (int m = 0; m < ens->n; ++m)
     if (!std::isfinite(dt[m])) return fail(DG_EINVAL, "dt must be finite");
-    ens->hmem[m].dt = dt[m];
-  }
-  hipError_t err = hipMemcpy(ens->d_mem, ens->hmem.data(), ens->n * sizeof(dgsw::EnsMember),
+  for (int m = 0; m < ens->n; ++m) ens->dt[m] = dt[m];
+  for (auto &it : ens->items) it.dt = dt[it.member];
+  hipError_t err = hipMemcpy(ens->d_items, ens->items.data(), ens->items.size() * sizeof(dgsw::EnsItem),
                              hipMemcpyHostToDevice);
   if (err != hipSuccess) return hip_fail(err, "upload of ensemble time steps");
   return DG_OK;
@@ -263,18 +328,21 @@ int dg_ens_rk_step(dg_ens *ens, void *q, void *work, int32_t nsteps, void *hip_s
   return DG_OK;
 }
 
-int dg_ens_set_schedule(dg_ens *ens, int32_t waves_per_group, int32_t groups) {
+int dg_ens_set_schedule(dg_ens *ens, int32_t waves_per_group, int32_t groups, int32_t fused) {
   if (!ens) return fail(DG_EINVAL, "ens is NULL");
   if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
     return fail(DG_EINVAL, "waves_per_group must be 1, 2 or 4");
-  if (groups < 1 || groups > (1 << 20)) return fail(DG_EINVAL, "groups out of range");
-  return upload_schedule(ens, waves_per_group, groups);
+  if (groups < 0 || groups > (1 << 20)) return fail(DG_EINVAL, "groups out of range");
+  if (fused != 0 && fused != 1) return fail(DG_EINVAL, "fused must be 0 or 1");
+  return upload_schedule(ens, waves_per_group, groups, fused);
 }
 
-int dg_ens_get_schedule(const dg_ens *ens, int32_t *waves_per_group, int32_t *groups) {
-  if (!ens || !waves_per_group || !groups) return fail(DG_EINVAL, "NULL argument");
+int dg_ens_get_schedule(const dg_ens *ens, int32_t *waves_per_group, int32_t *groups,
+                        int32_t *fused) {
+  if (!ens || !waves_per_group || !groups || !fused) return fail(DG_EINVAL, "NULL argument");
   *waves_per_group = ens->wpb;
   *groups = ens->parts;
+  *fused = ens->fused;
   return DG_OK;
 }
 
@@ -287,8 +355,8 @@ int dg_ens_autotune(dg_ens *ens, const void *q, void *work, const char *cache_pa
     while (std::getline(in, line)) {
       std::istringstream ls(line);
       std::string k;
-      int w = 0, p = 0;
-      if (ls >> k >> w >> p && k == key) return dg_ens_set_schedule(ens, w, p);
+      int w = 0, p = 0, f = 0;
+      if (ls >> k >> w >> p >> f && k == key) return dg_ens_set_schedule(ens, w, p, f);
     }
   }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -300,12 +368,13 @@ int dg_ens_autotune(dg_ens *ens, const void *q, void *work, const char *cache_pa
     return fail(DG_EHIP, "hipEventCreate");
   const int n_items = (int)ens->items.size();
   float best = 1e30f;
-  int best_w = ens->wpb, best_p = ens->parts;
+  int best_w = ens->wpb, best_p = ens->parts, best_f = ens->fused;
   int rc = DG_OK;
+  for (int f : {0, 1}) {
   for (int w : {1, 2, 4}) {
-    for (int p : {256, 512, 1024, 2048, 4096, 8192, 16384}) {
+    for (int p : {0, 256, 1024, 4096, 16384}) {
       if (p * w > 4 * n_items && p > 256) continue;
-      if ((rc = upload_schedule(ens, w, p)) != DG_OK) break;
+      if ((rc = upload_schedule(ens, w, p, f)) != DG_OK) break;
       float t_best = 1e30f;
       for (int rep = 0; rep < 4 && rc == DG_OK; ++rep) {
         (void)hipEventRecord(a, s);
@@ -322,17 +391,20 @@ int dg_ens_autotune(dg_ens *ens, const void *q, void *work, const char *cache_pa
         best = t_best;
         best_w = w;
         best_p = p;
+        best_f = f;
       }
     }
     if (rc != DG_OK) break;
   }
+  if (rc != DG_OK) break;
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (rc != DG_OK) return rc;
-  rc = upload_schedule(ens, best_w, best_p);
+  rc = upload_schedule(ens, best_w, best_p, best_f);
   if (rc == DG_OK && cache_path) {
     std::ofstream o(cache_path, std::ios::app);
-    o << key << " " << best_w << " " << best_p << "\n";
+    o << key << " " << best_w << " " << best_p << " " << best_f << "\n";
   }
   return rc;
 }

@@ -457,12 +457,26 @@ __global__ __launch_bounds__(64 * WPB) void k_dg_stage(StageArgs<T, NP> A, int s
   // another one
   __shared__ T tab_all[WPB][S_::TB];
   __shared__ T sh_all[WPB][(S_::GPW + 1) * S_::SH];
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int blk = xcd_block(blockIdx.x, gridDim.x) * WPB + wv;
   if (blk >= segs * A.n_lat) return;      // spare wavefront of the last workgroup
   const int j = blk / segs;
   stage_wave<T, NP>(A, j, blk - j * segs, threadIdx.x & 63, tab_all[wv], sh_all[wv]);
 }
+
+// expands to a switch over the runtime (dtype, np) that returns FN<T, NP>(args)
+#define DGSW_DISPATCH(dtype, np, FN, ...)                                              \
+  switch (np) {                                                                       \
+    case 1: return (dtype) == 0 ? FN<double, 1>(__VA_ARGS__) : FN<float, 1>(__VA_ARGS__); \
+    case 2: return (dtype) == 0 ? FN<double, 2>(__VA_ARGS__) : FN<float, 2>(__VA_ARGS__); \
+    case 3: return (dtype) == 0 ? FN<double, 3>(__VA_ARGS__) : FN<float, 3>(__VA_ARGS__); \
+    case 4: return (dtype) == 0 ? FN<double, 4>(__VA_ARGS__) : FN<float, 4>(__VA_ARGS__); \
+    case 5: return (dtype) == 0 ? FN<double, 5>(__VA_ARGS__) : FN<float, 5>(__VA_ARGS__); \
+    case 6: return (dtype) == 0 ? FN<double, 6>(__VA_ARGS__) : FN<float, 6>(__VA_ARGS__); \
+    case 7: return (dtype) == 0 ? FN<double, 7>(__VA_ARGS__) : FN<float, 7>(__VA_ARGS__); \
+    case 8: return (dtype) == 0 ? FN<double, 8>(__VA_ARGS__) : FN<float, 8>(__VA_ARGS__); \
+    default: break;                                                                   \
+  }
 
 // ------------------------------------------------------------------ ensemble
 // LDS of one wavefront for any order up to NPMAX
@@ -475,8 +489,8 @@ constexpr int lds_max_tab(int npmax) { return npmax == 0 ? 0 : (lds_tab(npmax) >
 constexpr int lds_max_sh(int npmax) { return npmax == 0 ? 0 : (lds_sh(npmax) > lds_max_sh(npmax - 1) ? lds_sh(npmax) : lds_max_sh(npmax - 1)); }
 
 template <typename T, int NP>
-__device__ __forceinline__ void ens_case(const EnsMember &m, const T *q, const T *q0, T *out,
-                                         int combine, T c0, T c1, int w, int lane, T *tab, T *sh) {
+__device__ __forceinline__ void ens_case(const EnsItem &m, const T *q, const T *q0, T *out,
+                                         int combine, T c0, T c1, int lane, T *tab, T *sh) {
   StageArgs<T, NP> A;
   A.q = q + m.off;
   A.q0 = q0 ? q0 + m.off : nullptr;
@@ -491,8 +505,7 @@ __device__ __forceinline__ void ens_case(const EnsMember &m, const T *q, const T
   A.c0 = c0;
   A.c1 = c1;
   A.dt = T(m.dt);
-  const int j = w / m.segs;
-  stage_wave<T, NP>(A, j, w - j * m.segs, lane, tab, sh);
+  stage_wave<T, NP>(A, m.j, m.seg, lane, tab, sh);
 }
 
 // One launch per Runge-Kutta stage for a whole ensemble of meshes of different
@@ -504,31 +517,29 @@ __device__ __forceinline__ void ens_case(const EnsMember &m, const T *q, const T
 // wave-uniform switch.
 template <typename T, int NPMAX, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_ens_stage(const T *__restrict__ q, const T *q0, T *out,
-                                                        const EnsMember *__restrict__ mem,
-                                                        const int2 *__restrict__ items,
+                                                        const EnsItem *__restrict__ items,
                                                         const int *__restrict__ bounds, int combine,
                                                         T c0, T c1) {
   __shared__ T tab_all[WPB][lds_max_tab(NPMAX)];
   __shared__ T sh_all[WPB][lds_max_sh(NPMAX)];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   T *tab = tab_all[wv], *sh = sh_all[wv];
   const int part = xcd_block(blockIdx.x, gridDim.x);
   const int end = bounds[part + 1];
   for (int it = bounds[part] + wv; it < end; it += WPB) {
-    const int2 w = items[it];
-    const EnsMember m = mem[w.x];
+    const EnsItem m = items[it];
     switch (m.np) {
-      case 1: ens_case<T, 1>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
-      case 2: ens_case<T, 2>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
-      case 3: ens_case<T, 3>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
-      case 4: ens_case<T, 4>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
-      case 5: ens_case<T, 5>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
+      case 1: ens_case<T, 1>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
+      case 2: ens_case<T, 2>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
+      case 3: ens_case<T, 3>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
+      case 4: ens_case<T, 4>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
+      case 5: ens_case<T, 5>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
       default:
         if constexpr (NPMAX > 5) {
           switch (m.np) {
-            case 6: ens_case<T, (NPMAX > 5 ? 6 : 1)>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
-            case 7: ens_case<T, (NPMAX > 6 ? 7 : 1)>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
-            case 8: ens_case<T, (NPMAX > 7 ? 8 : 1)>(m, q, q0, out, combine, c0, c1, w.y, lane, tab, sh); break;
+            case 6: ens_case<T, (NPMAX > 5 ? 6 : 1)>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
+            case 7: ens_case<T, (NPMAX > 6 ? 7 : 1)>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
+            case 8: ens_case<T, (NPMAX > 7 ? 8 : 1)>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
             default: break;
           }
         }
@@ -537,11 +548,86 @@ __global__ __launch_bounds__(64 * WPB) void k_ens_stage(const T *__restrict__ q,
   }
 }
 
+// Ensemble stage restricted to the members of one order (the work list is
+// sorted by order; bounds cover this order's items): the kernel is compiled for
+// that order alone, so it keeps that order's register budget and occupancy.
+template <typename T, int NP, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_ens_stage_np(const T *__restrict__ q, const T *q0, T *out,
+                                                           const EnsItem *__restrict__ items,
+                                                           const int *__restrict__ bounds, int combine,
+                                                           T c0, T c1) {
+  __shared__ T tab_all[WPB][Shape<T, NP>::TB];
+  __shared__ T sh_all[WPB][(Shape<T, NP>::GPW + 1) * Shape<T, NP>::SH];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int part = xcd_block(blockIdx.x, gridDim.x);
+  const int end = bounds[part + 1];
+  for (int it = bounds[part] + wv; it < end; it += WPB) {
+    const EnsItem m = items[it];
+    ens_case<T, NP>(m, q, q0, out, combine, c0, c1, lane, tab_all[wv], sh_all[wv]);
+  }
+}
+
+// Flat form: workgroup b takes items begin + b*WPB + wv, one item per
+// wavefront, so the hardware schedules the ensemble like an ordinary grid
+// (no loop: same register budget as the single-mesh kernel).
+template <typename T, int NP, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_ens_stage_flat(const T *__restrict__ q, const T *q0, T *out,
+                                                             const EnsItem *__restrict__ items,
+                                                             int begin, int end, int combine, T c0, T c1) {
+  __shared__ T tab_all[WPB][Shape<T, NP>::TB];
+  __shared__ T sh_all[WPB][(Shape<T, NP>::GPW + 1) * Shape<T, NP>::SH];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int it = begin + xcd_block(blockIdx.x, gridDim.x) * WPB + wv;
+  if (it >= end) return;
+  const EnsItem m = items[it];
+  ens_case<T, NP>(m, q, q0, out, combine, c0, c1, lane, tab_all[wv], sh_all[wv]);
+}
+
+template <typename T, int NP, int WPB>
+static hipError_t launch_ens_flat_t(const EnsLaunch &a, hipStream_t s) {
+  const int n = a.end - a.begin;
+  hipLaunchKernelGGL((k_ens_stage_flat<T, NP, WPB>), dim3((n + WPB - 1) / WPB), dim3(64 * WPB), 0, s,
+                     static_cast<const T *>(a.q), static_cast<const T *>(a.q0),
+                     static_cast<T *>(a.out), a.items, a.begin, a.end, a.combine, T(a.c0), T(a.c1));
+  return hipGetLastError();
+}
+
+template <typename T, int NP, int WPB>
+static hipError_t launch_ens_np_t(const EnsLaunch &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_ens_stage_np<T, NP, WPB>), dim3(a.parts), dim3(64 * WPB), 0, s,
+                     static_cast<const T *>(a.q), static_cast<const T *>(a.q0),
+                     static_cast<T *>(a.out), a.items, a.bounds, a.combine, T(a.c0), T(a.c1));
+  return hipGetLastError();
+}
+
+template <typename T, int NP>
+static hipError_t launch_ens_np_w(int wpb, const EnsLaunch &a, hipStream_t s) {
+  if (a.flat) {
+    switch (wpb) {
+      case 1: return launch_ens_flat_t<T, NP, 1>(a, s);
+      case 2: return launch_ens_flat_t<T, NP, 2>(a, s);
+      case 4: return launch_ens_flat_t<T, NP, 4>(a, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (wpb) {
+    case 1: return launch_ens_np_t<T, NP, 1>(a, s);
+    case 2: return launch_ens_np_t<T, NP, 2>(a, s);
+    case 4: return launch_ens_np_t<T, NP, 4>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_ens_stage_np(int dtype, int np, int wpb, const EnsLaunch &a, hipStream_t s) {
+  DGSW_DISPATCH(dtype, np, launch_ens_np_w, wpb, a, s)
+  return hipErrorInvalidValue;
+}
+
 template <typename T, int NPMAX, int WPB>
 static hipError_t launch_ens_t(const EnsLaunch &a, hipStream_t s) {
   hipLaunchKernelGGL((k_ens_stage<T, NPMAX, WPB>), dim3(a.parts), dim3(64 * WPB), 0, s,
                      static_cast<const T *>(a.q), static_cast<const T *>(a.q0),
-                     static_cast<T *>(a.out), a.mem, a.items, a.bounds, a.combine, T(a.c0), T(a.c1));
+                     static_cast<T *>(a.out), a.items, a.bounds, a.combine, T(a.c0), T(a.c1));
   return hipGetLastError();
 }
 
@@ -659,20 +745,6 @@ static hipError_t launch_mass_t(const void *q, const double *mw, int n_lon, int 
   hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(kMassThreads), 0, s, partial, kMassBlocks, out4);
   return hipGetLastError();
 }
-
-// expands to a switch over the runtime (dtype, np) that returns FN<T, NP>(args)
-#define DGSW_DISPATCH(dtype, np, FN, ...)                                              \
-  switch (np) {                                                                       \
-    case 1: return (dtype) == 0 ? FN<double, 1>(__VA_ARGS__) : FN<float, 1>(__VA_ARGS__); \
-    case 2: return (dtype) == 0 ? FN<double, 2>(__VA_ARGS__) : FN<float, 2>(__VA_ARGS__); \
-    case 3: return (dtype) == 0 ? FN<double, 3>(__VA_ARGS__) : FN<float, 3>(__VA_ARGS__); \
-    case 4: return (dtype) == 0 ? FN<double, 4>(__VA_ARGS__) : FN<float, 4>(__VA_ARGS__); \
-    case 5: return (dtype) == 0 ? FN<double, 5>(__VA_ARGS__) : FN<float, 5>(__VA_ARGS__); \
-    case 6: return (dtype) == 0 ? FN<double, 6>(__VA_ARGS__) : FN<float, 6>(__VA_ARGS__); \
-    case 7: return (dtype) == 0 ? FN<double, 7>(__VA_ARGS__) : FN<float, 7>(__VA_ARGS__); \
-    case 8: return (dtype) == 0 ? FN<double, 8>(__VA_ARGS__) : FN<float, 8>(__VA_ARGS__); \
-    default: break;                                                                   \
-  }
 
 hipError_t launch_stage(int dtype, int np, const StageLaunch &a, hipStream_t s) {
   DGSW_DISPATCH(dtype, np, launch_stage_t, a, s)

@@ -106,8 +106,8 @@ def test_schedule_does_not_change_results(dg):
     ens, q, dts = build(dg, "f32")
     ref = ens.empty_state()
     ens.rk_stage(q, None, ref, 0.0, 1.0)
-    for w, g in [(1, 1), (1, 7), (2, 64), (4, 3), (4, 1000), (2, 100000)]:
-        ens.set_schedule(w, g)
+    for w, g, f in [(1, 1, 0), (1, 7, 1), (2, 64, 0), (4, 3, 1), (4, 1000, 0), (2, 100000, 1), (4, 0, 0), (2, 0, 1)]:
+        ens.set_schedule(w, g, f)
         out = ens.empty_state()
         ens.rk_stage(q, None, out, 0.0, 1.0)
         assert torch.equal(out, ref), (w, g)
@@ -117,11 +117,11 @@ def test_autotune_and_cache(dg, tmp_path):
     say("autotune")
     ens, q, dts = build(dg, "f32")
     path = str(tmp_path / "tune.txt")
-    w, g = ens.autotune(q, ens.empty_work(), path)
+    w, g, f = ens.autotune(q, ens.empty_work(), path)
     assert w in (1, 2, 4) and g >= 1
-    assert os.path.exists(path) and len(open(path).read().split()) == 3
-    ens.set_schedule(1, 1)
-    assert ens.autotune(q, ens.empty_work(), path) == (w, g)
+    assert os.path.exists(path) and len(open(path).read().split()) == 4
+    ens.set_schedule(1, 1, not f)
+    assert ens.autotune(q, ens.empty_work(), path) == (w, g, f)
 
 
 def test_graph_replays_match_eager(dg):
