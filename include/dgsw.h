@@ -216,6 +216,69 @@ int dg_graph_ens(dg_ens *ens, void *q, void *work, int32_t nsteps, dg_graph **ou
 int dg_graph_launch(dg_graph *graph, void *hip_stream);
 int dg_graph_free(dg_graph *graph);
 
+/* ---------------------------------------------------------------------------
+ * Learned right-hand-side correction (an addition to the paper's method): a
+ * network 108 -> 256 -> 256 -> 12 with GELU (erf form) after the hidden layers,
+ * BF16 operands and FP32 accumulation on the matrix cores, maps the 3 x 3
+ * element stencil of an r = 1 state (3 variables x 4 modes per element,
+ * periodic in longitude, the pole row repeated across a pole) to a correction
+ * of the element's r = 1 right-hand side.
+ *
+ * Parameters: one FP32 vector of dg_mlp_param_count values, in order
+ * W1[108][256], b1[256], W2[256][256], b2[256], W3[256][12], b3[12]
+ * (W[k][n] maps input k to output n).  Feature k of element (i, j) is
+ * q[(j+dj, i+di)][v][m] with k = ((dj+1)*3 + (di+1))*12 + v*4 + m.
+ * ------------------------------------------------------------------------- */
+int dg_mlp_param_count(int64_t *n);
+/* Device workspace bytes of dg_mlp_forward / dg_mlp_train_step for `rows`. */
+int dg_mlp_workspace_size(int64_t rows, int64_t *bytes);
+/* Y[rows][12] = net(X[rows][108]) (FP32 in and out, device). */
+int dg_mlp_forward(const float *params, const float *X, int64_t rows, float *Y, void *workspace,
+                   void *hip_stream);
+/* Forward and backward pass of the mean squared error over the outputs with
+ * mask[n] = 1 (mask: 12 device floats, 0 or 1) against T[rows][12]; rows a
+ * multiple of 32.  grads (optional, device, param_count floats) receives the
+ * gradient; loss (optional, device float) the mean squared error; with
+ * lr > 0 one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with
+ * the 1-based step) updates params, adam_m, adam_v in place.  Synchronises
+ * hip_stream once (to read the mask). */
+int dg_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t step, float lr,
+                      const float *X, const float *T, const float *mask, int64_t rows,
+                      float *grads, float *loss, void *workspace, void *hip_stream);
+/* Cos-weighted L2 projection of a state of any order onto order 1 on the
+ * same mesh (dst must have order 1, same mesh and dtype). */
+int dg_project(const dg_ctx *src, const dg_ctx *dst, const void *q_src, void *q_dst,
+               void *hip_stream);
+/* Stencil features X[E][108] (FP32, device) of an order-1 state, standardised
+ * as (x - mean[k]) * istd[k] when both are given (else raw). */
+int dg_features(const dg_ctx *ctx, const void *q, const float *feat_mean,
+                const float *feat_istd, float *X, void *hip_stream);
+
+/* The learned right-hand side on an order-1 context: L(q) = L1(q) + c(q), with
+ * c = out_mean[j] + out_std[j] * net(standardised features) per element of
+ * latitude row j.  Trust bound: an element whose correction is not finite, or
+ * exceeds kappa * max|L1| over the modes of some variable, falls back to the
+ * plain L1 (and is counted).  The (h, mode 00) output of the network is not
+ * used: it is replaced by one constant for all elements that makes the total
+ * h-mass change of the correction exactly zero. */
+typedef struct {
+  const float *params;      /* device, dg_mlp_param_count floats                  */
+  const float *feat_mean;   /* device, 108 floats                                  */
+  const float *feat_istd;   /* device, 108 floats                                  */
+  const float *out_mean;    /* device, [n_lat][12]                                 */
+  const float *out_std;     /* device, [n_lat][12]                                 */
+  double kappa;             /* trust bound, >= 0                                   */
+} dg_learned;
+int dg_learned_workspace_size(const dg_ctx *ctx, int64_t *bytes);
+/* dqdt = L1(q) + c(q).  fallbacks: optional device int32 incremented by the
+ * number of elements that fell back. */
+int dg_rhs_learned(dg_ctx *ctx, const dg_learned *net, const void *q, void *dqdt,
+                   void *workspace, int32_t *fallbacks, void *hip_stream);
+/* nsteps SSP-RK3 steps with the learned right-hand side (work: 2 states). */
+int dg_rk_step_learned(dg_ctx *ctx, const dg_learned *net, void *q, void *work,
+                       void *workspace, double dt, int32_t nsteps, int32_t *fallbacks,
+                       void *hip_stream);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char *dg_last_error(void);
 

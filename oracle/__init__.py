@@ -7,6 +7,11 @@ baseline leg of the benchmark may import it.  The product path (the C-ABI
 library and its Python binding) never imports, calls or falls back to it,
 and this package imports nothing from the product.
 
+``mlp`` is the oracle of the learned right-hand-side correction, an addition
+to the paper's method (a small network that corrects the r = 1 right-hand
+side towards the projection of higher-order runs); it is pinned by finite
+differences and library routines.
+
 Every function here is pinned by tests against facts that do not come from
 the oracle itself (quadrature exactness, closed forms, a textbook first-order
 finite-volume scheme at r = 0, lake at rest, conservation, symmetries,
@@ -14,7 +19,8 @@ convergence of the operator on smooth fields, Runge-Kutta stability
 polynomials and the paper's printed Butcher tableaux).
 """
 from .basis import gauss_legendre, legendre
-from .sphere import SphereDG
+from .sphere import SphereDG, project_order
+from . import mlp
 from .timestep import ssp_rk3, butcher_step
 
-__all__ = ["gauss_legendre", "legendre", "SphereDG", "ssp_rk3", "butcher_step"]
+__all__ = ["gauss_legendre", "legendre", "SphereDG", "project_order", "ssp_rk3", "butcher_step", "mlp"]

@@ -343,3 +343,27 @@ class SphereDG:
         (3 components, no cos weight): the modal form of a forcing term
         added to the right-hand side of the conservative system."""
         return self.project(lambda lam, th: np.asarray(fun(lam, th)) / np.cos(th), extra)
+
+
+def project_order(q_src, src, dst, extra=9):
+    """Cos-weighted L2 projection of a modal state on mesh `src` onto the
+    basis of `dst` (same mesh, another order): q_dst = M_dst^-1 int q_src
+    phi_dst cos(theta), by Gauss-Legendre quadrature exact for the product
+    of the two polynomial degrees times cos over one latitude row."""
+    assert (src.n_lon, src.n_lat) == (dst.n_lon, dst.n_lat)
+    nq = src.n + dst.n + extra
+    xq, wq = gauss_legendre(nq)
+    Ps, _ = legendre(src.order, xq)                     # [q, a]
+    Pd, _ = legendre(dst.order, xq)
+    # phi at the 2-D points: [point (s, p), mode (b, a)]
+    phis = np.einsum("pa,sb->spba", Ps, Ps).reshape(nq * nq, src.N)
+    phid = np.einsum("pa,sb->spba", Pd, Pd).reshape(nq * nq, dst.N)
+    q = src.grid(q_src)
+    out = np.empty((dst.n_lat, dst.n_lon, 3, dst.N))
+    for j in range(dst.n_lat):
+        th = dst.theta_edge[j] + (1.0 + xq) * 0.5 * dst.dth
+        wt = (np.outer(wq * np.cos(th), wq)).reshape(-1)   # [s, p]
+        C = 0.25 * dst.dlam * dst.dth * (phid.T * wt) @ phis   # [m_dst, m_src]
+        b = np.einsum("mn,ivn->ivm", C, q[j])
+        out[j] = np.linalg.solve(dst.M[j], b.reshape(-1, dst.N).T).T.reshape(dst.n_lon, 3, dst.N)
+    return out.reshape(dst.E, 3, dst.N)

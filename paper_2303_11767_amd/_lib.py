@@ -27,7 +27,15 @@ EXPORTS = ("dg_init_mesh", "dg_free", "dg_state_size", "dg_work_size", "dg_min_w
            "dg_ens_init", "dg_ens_free", "dg_ens_state_size", "dg_ens_offsets", "dg_ens_member",
            "dg_ens_set_dt", "dg_ens_rhs", "dg_ens_rk_stage", "dg_ens_rk_step", "dg_ens_set_schedule",
            "dg_ens_get_schedule", "dg_ens_autotune", "dg_graph_rk", "dg_graph_ens",
-           "dg_graph_launch", "dg_graph_free")
+           "dg_graph_launch", "dg_graph_free", "dg_mlp_param_count", "dg_mlp_workspace_size",
+           "dg_mlp_forward", "dg_mlp_train_step", "dg_project", "dg_features",
+           "dg_learned_workspace_size", "dg_rhs_learned", "dg_rk_step_learned")
+
+
+class Learned(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("feat_mean", ctypes.c_void_p),
+                ("feat_istd", ctypes.c_void_p), ("out_mean", ctypes.c_void_p),
+                ("out_std", ctypes.c_void_p), ("kappa", ctypes.c_double)]
 
 
 class DGError(RuntimeError):
@@ -87,6 +95,17 @@ def load():
     lib.dg_graph_ens.argtypes = [vp, vp, vp, i32, ctypes.POINTER(vp)]
     lib.dg_graph_launch.argtypes = [vp, vp]
     lib.dg_graph_free.argtypes = [vp]
+    lib.dg_mlp_param_count.argtypes = [i64p]
+    lib.dg_mlp_workspace_size.argtypes = [ctypes.c_int64, i64p]
+    lib.dg_mlp_forward.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
+    lib.dg_mlp_train_step.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, ctypes.c_int64,
+                                      vp, vp, vp, vp]
+    lib.dg_project.argtypes = [vp, vp, vp, vp, vp]
+    lib.dg_features.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.dg_learned_workspace_size.argtypes = [vp, i64p]
+    lib.dg_rhs_learned.argtypes = [vp, ctypes.POINTER(Learned), vp, vp, vp, vp, vp]
+    lib.dg_rk_step_learned.argtypes = [vp, ctypes.POINTER(Learned), vp, vp, vp, ctypes.c_double, i32,
+                                       vp, vp]
     lib.dg_last_error.argtypes = []
     lib.dg_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdgsw.so")
-SOURCES = ["dgsw_tables.cpp", "dgsw_kernels.hip", "dgsw_api.hip", "dgsw_ensemble.hip"]
+SOURCES = ["dgsw_tables.cpp", "dgsw_kernels.hip", "dgsw_api.hip", "dgsw_ensemble.hip",
+           "dgsw_mlp.hip", "dgsw_learned.hip"]
 ARCH = os.environ.get("DGSW_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

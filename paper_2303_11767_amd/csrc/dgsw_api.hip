@@ -46,6 +46,7 @@ void release(dg_ctx *c) {
   if (c->d_mass_w) (void)hipFree(c->d_mass_w);
   if (c->d_partial) (void)hipFree(c->d_partial);
   if (c->d_out4) (void)hipFree(c->d_out4);
+  if (c->d_proj1) (void)hipFree(c->d_proj1);
   delete c;
 }
 
@@ -116,12 +117,32 @@ int dg_init_mesh(const dg_mesh_desc *desc, void *hip_stream, dg_ctx **out) {
                   desc->alpha_mode == DG_ALPHA_GLOBAL ? desc->alpha : 0.0, hg.data());
   dgsw::fill_rows(dt, c->np, t, hr.data());
 
+  // projection onto order 1 on the same mesh: P_j = M1_j^-1 Mth_j[0..1][:],
+  // M1_j the leading 2 x 2 block of the latitude mass matrix (orders 0, 1)
+  const int npp = c->np;
+  std::vector<double> proj((size_t)desc->n_lat * 2 * npp, 0.0);
+  for (int j = 0; j < desc->n_lat; ++j) {
+    const double *Mj = &t.Mth[(size_t)j * npp * npp];
+    c->mass_area += desc->n_lon * t.mass_w[(size_t)j * npp + 0];
+    if (npp == 1) {
+      proj[(size_t)j * 2 * npp + 0] = 1.0;   // order 0: the constant maps to mode 00
+      continue;
+    }
+    const double a = Mj[0], b = Mj[1], cc = Mj[npp], d = Mj[npp + 1];
+    const double det = a * d - b * cc;
+    const double inv[4] = {d / det, -b / det, -cc / det, a / det};
+    for (int r = 0; r < 2; ++r)
+      for (int bb = 0; bb < npp; ++bb)
+        proj[((size_t)j * 2 + r) * npp + bb] = inv[r * 2 + 0] * Mj[0 * npp + bb] + inv[r * 2 + 1] * Mj[1 * npp + bb];
+  }
+
   hipError_t e;
   if ((e = hipMalloc(&c->d_glob, gb)) != hipSuccess ||
       (e = hipMalloc(&c->d_rows, rb)) != hipSuccess ||
       (e = hipMalloc(reinterpret_cast<void **>(&c->d_mass_w), t.mass_w.size() * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(reinterpret_cast<void **>(&c->d_partial), dgsw::mass_blocks() * 4 * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(reinterpret_cast<void **>(&c->d_out4), 4 * sizeof(double))) != hipSuccess) {
+      (e = hipMalloc(reinterpret_cast<void **>(&c->d_out4), 4 * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void **>(&c->d_proj1), proj.size() * sizeof(double))) != hipSuccess) {
     release(c);
     return fail(DG_ENOMEM, std::string("hipMalloc of context tables: ") + hipGetErrorString(e));
   }
@@ -129,6 +150,8 @@ int dg_init_mesh(const dg_mesh_desc *desc, void *hip_stream, dg_ctx **out) {
       (e = hipMemcpyAsync(c->d_rows, hr.data(), rb, hipMemcpyHostToDevice, s)) != hipSuccess ||
       (e = hipMemcpyAsync(c->d_mass_w, t.mass_w.data(), t.mass_w.size() * sizeof(double),
                           hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(c->d_proj1, proj.data(), proj.size() * sizeof(double), hipMemcpyHostToDevice,
+                          s)) != hipSuccess ||
       (e = hipStreamSynchronize(s)) != hipSuccess) {
     release(c);
     return hip_fail(e, "upload of context tables");

@@ -20,6 +20,8 @@ struct dg_ctx {
   double *d_out4 = nullptr;    // mass result
   const void *forcing = nullptr;
   double min_width = 0.0;
+  double *d_proj1 = nullptr;   // [n_lat][2][np]: cos-weighted projection onto order 1
+  double mass_area = 0.0;      // sum over elements of mass_w[j][0]
 };
 
 namespace dgsw {

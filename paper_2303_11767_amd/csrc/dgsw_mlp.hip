@@ -1,0 +1,502 @@
+// Learned right-hand-side correction: a 108 -> 256 -> 256 -> 12 GELU network
+// in BF16 with FP32 accumulation on the gfx950 matrix cores (v_mfma 16x16x32
+// bf16), its backward pass and Adam, the 3x3-stencil features of an r = 1
+// state, and the learned stage (plain r = 1 right-hand side + correction, with
+// a per-element trust bound and a global mass correction).
+//
+// MFMA 16x16x32 bf16 operand layout (lane l of 64): A[row = l%16][k = 8(l/16)+j],
+// B[k = 8(l/16)+j][col = l%16], j = 0..7; result C[row = 4(l/16)+i][col = l%16],
+// i = 0..3.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "dgsw_ctx.hpp"
+#include "dgsw_device.hpp"
+#include "dgsw_mlp.hpp"
+
+namespace dgsw {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+// ------------------------------------------------------------------ GEMM
+// C[M][N] = A(m, k) B(k, n) over k < K (K % 32 == 0, N % 32 == 0), with
+//   A_KC: A(m, k) = A[m * lda + k]   (else A[k * lda + m])
+//   B_KC: B(k, n) = B[n * ldb + k]   (else B[k * ldb + n])
+// A workgroup of 4 wavefronts computes a 64 x 64 tile, a wavefront 32 x 32
+// (2 x 2 MFMA tiles); rows >= M are read clamped and not written.
+template <bool A_KC, bool B_KC, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, const __bf16 *__restrict__ B,
+                                              int M, int N, int K, int lda, int ldb,
+                                              const float *__restrict__ bias,
+                                              const float *__restrict__ Zin, float *__restrict__ Zout,
+                                              void *__restrict__ C, int ldc) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int m0 = blockIdx.x * 64 + (wv >> 1) * 32;
+  const int n0 = blockIdx.y * 64 + (wv & 1) * 32;
+  if (n0 >= N) return;
+  const int r = lane & 15, kq = (lane >> 4) * 8;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int ma[2], nb[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int m = m0 + 16 * i + r;
+    ma[i] = m < M ? m : M - 1;
+    nb[i] = n0 + 16 * i + r;
+  }
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      if constexpr (A_KC) {
+        a[i] = *reinterpret_cast<const bf16x8 *>(A + (size_t)ma[i] * lda + k0 + kq);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[i][j] = A[(size_t)(k0 + kq + j) * lda + ma[i]];
+      }
+      if constexpr (B_KC) {
+        b[i] = *reinterpret_cast<const bf16x8 *>(B + (size_t)nb[i] * ldb + k0 + kq);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) b[i][j] = B[(size_t)(k0 + kq + j) * ldb + nb[i]];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+  // epilogue: lane holds rows 4(l/16)+e of each 16 x 16 tile, column l%16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = m0 + 16 * i + (lane >> 4) * 4 + e;
+        const int n = n0 + 16 * j + r;
+        if (m >= M) continue;
+        float z = acc[i][j][e];
+        const size_t o = (size_t)m * ldc + n;
+        if constexpr (EPI == kEpiBiasGelu) {
+          z += bias[n];
+          if (Zout) Zout[o] = z;
+          static_cast<__bf16 *>(C)[o] = (__bf16)gelu_f(z);
+        } else if constexpr (EPI == kEpiBias) {
+          static_cast<float *>(C)[o] = z + bias[n];
+        } else if constexpr (EPI == kEpiGeluGrad) {
+          z *= gelu_grad_f(Zin[o]);
+          if (Zout) Zout[o] = z;
+          static_cast<__bf16 *>(C)[o] = (__bf16)z;
+        } else {
+          static_cast<float *>(C)[o] = z;
+        }
+      }
+}
+
+template <bool A_KC, bool B_KC, int EPI>
+static hipError_t gemm_t(const GemmArgs &g, hipStream_t s) {
+  dim3 grid((g.M + 63) / 64, (g.N + 63) / 64);
+  hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI>), grid, dim3(256), 0, s, g.A, g.B, g.M, g.N, g.K, g.lda,
+                     g.ldb, g.bias, g.Zin, g.Zout, g.C, g.ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(bool a_kc, bool b_kc, int epi, const GemmArgs &g, hipStream_t s) {
+  if (g.M <= 0) return hipSuccess;
+  if (g.K % 32 || g.N % 32) return hipErrorInvalidValue;
+#define DGSW_GEMM(AK, BK, E) \
+  if (a_kc == AK && b_kc == BK && epi == E) return gemm_t<AK, BK, E>(g, s);
+  DGSW_GEMM(true, true, kEpiBiasGelu) DGSW_GEMM(true, true, kEpiBias)
+  DGSW_GEMM(true, true, kEpiGeluGrad) DGSW_GEMM(true, true, kEpiPlain)
+  DGSW_GEMM(false, false, kEpiPlain)
+#undef DGSW_GEMM
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ weights
+// FP32 parameter vector -> BF16 operand copies: Wt[n][kp] (forward, k
+// contiguous, k padded with zeros to kp) and Wr[k][np] (backward, rows padded
+// to the next layer's padded width np, columns beyond n zero).
+__global__ void k_prep_weights(const float *__restrict__ W, int k_in, int n_out, int kp, int np_,
+                               __bf16 *__restrict__ Wt, __bf16 *__restrict__ Wr) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = kp * np_;
+  if (idx >= total) return;
+  const int k = idx / np_, n = idx - k * np_;
+  const float w = (k < k_in && n < n_out) ? W[(size_t)k * n_out + n] : 0.0f;
+  if (Wr) Wr[(size_t)k * np_ + n] = (__bf16)w;
+  if (Wt) Wt[(size_t)n * kp + k] = (__bf16)w;
+}
+
+hipError_t launch_prep_weights(const float *W, int k_in, int n_out, int kp, int np_, __bf16 *Wt, __bf16 *Wr,
+                               hipStream_t s) {
+  const int total = kp * np_;
+  hipLaunchKernelGGL(k_prep_weights, dim3((total + 255) / 256), dim3(256), 0, s, W, k_in, n_out, kp, np_, Wt, Wr);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ loss
+// dY = 2 (Y - T) mask / (rows * sum(mask)) as BF16 (padded columns zero) and
+// the squared error summed per block into partial[blockIdx.x].
+__global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ Y, const float *__restrict__ T,
+                                                  const float *__restrict__ mask, int rows, int n_out, int ld,
+                                                  float scale, __bf16 *__restrict__ dY, float *__restrict__ dYf,
+                                                  float *__restrict__ partial) {
+  __shared__ float sh[256];
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  float se = 0.f;
+  if (idx < rows * ld) {
+    const int m = idx / ld, n = idx - m * ld;
+    float g = 0.f;
+    if (n < n_out) {
+      const float d = (Y[(size_t)m * ld + n] - T[(size_t)m * n_out + n]) * mask[n];
+      se = d * d;
+      g = 2.f * d * scale;
+    }
+    dY[idx] = (__bf16)g;
+    dYf[idx] = g;
+  }
+  sh[threadIdx.x] = se;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+hipError_t launch_mse_grad(const float *Y, const float *T, const float *mask, int rows, int n_out, int ld, float scale,
+                           __bf16 *dY, float *dYf, float *partial, int *nblocks, hipStream_t s) {
+  *nblocks = (rows * ld + 255) / 256;
+  hipLaunchKernelGGL(k_mse_grad, dim3(*nblocks), dim3(256), 0, s, Y, T, mask, rows, n_out, ld, scale, dY, dYf, partial);
+  return hipGetLastError();
+}
+
+// Column sums of G[rows][ld] for the first n columns (bias gradients), one
+// thread per column, rows in order (deterministic).
+__global__ void k_colsum(const float *__restrict__ G, int rows, int n, int ld, float *__restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  float acc = 0.f;
+  for (int m = 0; m < rows; ++m) acc += G[(size_t)m * ld + c];
+  out[c] = acc;
+}
+
+hipError_t launch_colsum(const float *G, int rows, int n, int ld, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_colsum, dim3((n + 63) / 64), dim3(64), 0, s, G, rows, n, ld, out);
+  return hipGetLastError();
+}
+
+// scale * (sum of `n` partials), single block, fixed order, into *out.
+__global__ __launch_bounds__(256) void k_sum(const float *__restrict__ p, int n, float scale,
+                                             float *__restrict__ out) {
+  __shared__ float sh[256];
+  float acc = 0.f;
+  for (int k = threadIdx.x; k < n; k += 256) acc += p[k];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = scale * sh[0];
+}
+
+hipError_t launch_sum(const float *p, int n, float scale, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, p, n, scale, out);
+  return hipGetLastError();
+}
+
+// X[rows][n] (FP32) -> Xb[rows][ldx] (BF16, columns >= n zero)
+__global__ void k_to_bf16(const float *__restrict__ X, int rows, int n, int ldx, __bf16 *__restrict__ Xb) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)rows * ldx) return;
+  const size_t m = idx / ldx;
+  const int k = (int)(idx - m * ldx);
+  Xb[idx] = (__bf16)(k < n ? X[m * n + k] : 0.0f);
+}
+
+hipError_t launch_to_bf16(const float *X, int rows, int n, int ldx, __bf16 *Xb, hipStream_t s) {
+  const size_t total = (size_t)rows * ldx;
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, X, rows, n, ldx, Xb);
+  return hipGetLastError();
+}
+
+// b[n] -> out[np_] with zeros beyond n
+__global__ void k_pad(const float *__restrict__ b, int n, int np_, float *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < np_) out[i] = i < n ? b[i] : 0.0f;
+}
+
+hipError_t launch_pad(const float *b, int n, int np_, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pad, dim3((np_ + 63) / 64), dim3(64), 0, s, b, n, np_, out);
+  return hipGetLastError();
+}
+
+// Gradient of a weight matrix W[k_in][n_out] from the padded GEMM result
+// G[kp][np_] (rows/cols beyond the real sizes dropped) into the flat vector.
+__global__ void k_unpad(const float *__restrict__ G, int k_in, int n_out, int np_, float *__restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= k_in * n_out) return;
+  const int k = idx / n_out, n = idx - k * n_out;
+  out[idx] = G[(size_t)k * np_ + n];
+}
+
+hipError_t launch_unpad(const float *G, int k_in, int n_out, int np_, float *out, hipStream_t s) {
+  const int total = k_in * n_out;
+  hipLaunchKernelGGL(k_unpad, dim3((total + 255) / 256), dim3(256), 0, s, G, k_in, n_out, np_, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Adam
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s) {
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ features
+// X[e][k] = bf16((q1[nb(e, k)][v][m] - mean[k]) * istd[k]) for the 3 x 3 stencil
+// of an r = 1 state (periodic in longitude, pole row repeated across a pole),
+// k = ((dj+1)*3 + (di+1))*12 + v*4 + m; columns 108..ldx-1 are zero.
+template <typename T>
+__global__ void k_features(const T *__restrict__ q, int n_lon, int n_lat, const float *__restrict__ mean,
+                           const float *__restrict__ istd, int ldx, __bf16 *__restrict__ X) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t E = (size_t)n_lon * n_lat;
+  if (idx >= E * ldx) return;
+  const int e = (int)(idx / ldx), k = (int)(idx - (size_t)e * ldx);
+  float x = 0.f;
+  if (k < kFeatures) {
+    const int s = k / 12, vm = k - s * 12;
+    const int dj = s / 3 - 1, di = s % 3 - 1;
+    const int j = e / n_lon, i = e - j * n_lon;
+    int jj = j + dj;
+    jj = jj < 0 ? 0 : (jj >= n_lat ? n_lat - 1 : jj);
+    int ii = i + di;
+    ii = ii < 0 ? ii + n_lon : (ii >= n_lon ? ii - n_lon : ii);
+    x = ((float)q[((size_t)jj * n_lon + ii) * 12 + vm] - mean[k]) * istd[k];
+  }
+  X[idx] = (__bf16)x;
+}
+
+// Same features in FP32, [E][108], standardised when mean/istd are given.
+template <typename T>
+__global__ void k_features_f32(const T *__restrict__ q, int n_lon, int n_lat, const float *__restrict__ mean,
+                               const float *__restrict__ istd, float *__restrict__ X) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t E = (size_t)n_lon * n_lat;
+  if (idx >= E * kFeatures) return;
+  const int e = (int)(idx / kFeatures), k = (int)(idx - (size_t)e * kFeatures);
+  const int s = k / 12, vm = k - s * 12;
+  const int dj = s / 3 - 1, di = s % 3 - 1;
+  const int j = e / n_lon, i = e - j * n_lon;
+  int jj = j + dj;
+  jj = jj < 0 ? 0 : (jj >= n_lat ? n_lat - 1 : jj);
+  int ii = i + di;
+  ii = ii < 0 ? ii + n_lon : (ii >= n_lon ? ii - n_lon : ii);
+  float x = (float)q[((size_t)jj * n_lon + ii) * 12 + vm];
+  if (mean) x = (x - mean[k]) * istd[k];
+  X[idx] = x;
+}
+
+hipError_t launch_features_f32(int dtype, const void *q, int n_lon, int n_lat, const float *mean, const float *istd,
+                               float *X, hipStream_t s) {
+  const size_t total = (size_t)n_lon * n_lat * kFeatures;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_features_f32<double>, grid, dim3(256), 0, s, static_cast<const double *>(q), n_lon, n_lat,
+                       mean, istd, X);
+  else
+    hipLaunchKernelGGL(k_features_f32<float>, grid, dim3(256), 0, s, static_cast<const float *>(q), n_lon, n_lat,
+                       mean, istd, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_features(int dtype, const void *q, int n_lon, int n_lat, const float *mean, const float *istd,
+                           int ldx, __bf16 *X, hipStream_t s) {
+  const size_t total = (size_t)n_lon * n_lat * ldx;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_features<double>, grid, dim3(256), 0, s, static_cast<const double *>(q), n_lon, n_lat, mean,
+                       istd, ldx, X);
+  else
+    hipLaunchKernelGGL(k_features<float>, grid, dim3(256), 0, s, static_cast<const float *>(q), n_lon, n_lat, mean,
+                       istd, ldx, X);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ learned stage
+// Correction of element e from the network output Y[e][0..11] (standardised):
+// c = mean_j + std_j * Y; rejected (c = 0, counted) if non-finite or if, for
+// some variable, max |c| > kappa max |L1| over its 4 modes.  The (h, mode 00)
+// output is not predicted: it is set by the global mass correction.  Block
+// partial sums of the element masses of the h-correction go to partial[].
+template <typename T>
+__global__ __launch_bounds__(256) void k_correction(const float *__restrict__ Y, int ldy, const T *__restrict__ L1,
+                                                    const float *__restrict__ omean, const float *__restrict__ ostd,
+                                                    const double *__restrict__ mass_w, int n_lon, int E, float kappa,
+                                                    float *__restrict__ C, double *__restrict__ partial,
+                                                    int *__restrict__ fallback) {
+  __shared__ double sh[256];
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  double mass = 0.0;
+  if (e < E) {
+    const int j = e / n_lon;
+    float c[12];
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      c[k] = k == 0 ? 0.f : omean[j * 12 + k] + ostd[j * 12 + k] * Y[(size_t)e * ldy + k];
+      ok = ok && isfinite(c[k]);
+    }
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      float mc = 0.f, ml = 0.f;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        mc = fmaxf(mc, fabsf(c[v * 4 + m]));
+        ml = fmaxf(ml, fabsf((float)L1[(size_t)e * 12 + v * 4 + m]));
+      }
+      ok = ok && !(mc > kappa * ml);
+    }
+    if (!ok) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) c[k] = 0.f;
+      if (fallback) atomicAdd(fallback, 1);
+    }
+    // element mass of the h-correction: modes (a = 0, b = 0) and (a = 0, b = 1) = 0 and 2
+    mass = mass_w[j * 2 + 1] * (double)c[2];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) C[(size_t)e * 12 + k] = c[k];
+  }
+  sh[threadIdx.x] = mass;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// delta = -(sum of partials) / (sum over elements of mass_w[j][0]): the mode-00
+// h-correction that makes the total h-mass change of the correction zero.
+__global__ __launch_bounds__(256) void k_mass_delta(const double *__restrict__ partial, int nparts,
+                                                    double area, float *__restrict__ delta) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += 256) acc += partial[k];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *delta = (float)(-sh[0] / area);
+}
+
+// out = combine ? c0 q0 + c1 (q + dt (L1 + c)) : L1 + c, with c_(h,00) = delta.
+template <typename T>
+__global__ __launch_bounds__(256) void k_learned_out(const T *__restrict__ q, const T *q0, const T *__restrict__ L1,
+                                                     const float *__restrict__ C, const float *__restrict__ delta,
+                                                     int E, int combine, T c0, T c1, T dt, T *out) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= E * 12) return;
+  const int k = idx % 12;
+  const T corr = k == 0 ? (T)(*delta) : (T)C[idx];
+  const T l = L1[idx] + corr;
+  if (combine) {
+    const T qn = c0 != T(0) ? q0[idx] : T(0);
+    out[idx] = c0 * qn + c1 * (q[idx] + dt * l);
+  } else {
+    out[idx] = l;
+  }
+}
+
+hipError_t launch_correction(int dtype, const LearnedLaunch &a, hipStream_t s) {
+  const int blocks = (a.E + 255) / 256;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_correction<double>, dim3(blocks), dim3(256), 0, s, a.Y, a.ldy,
+                       static_cast<const double *>(a.L1), a.omean, a.ostd, a.mass_w, a.n_lon, a.E, a.kappa, a.C,
+                       a.partial, a.fallback);
+  else
+    hipLaunchKernelGGL(k_correction<float>, dim3(blocks), dim3(256), 0, s, a.Y, a.ldy,
+                       static_cast<const float *>(a.L1), a.omean, a.ostd, a.mass_w, a.n_lon, a.E, a.kappa, a.C,
+                       a.partial, a.fallback);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_mass_delta, dim3(1), dim3(256), 0, s, a.partial, blocks, a.area, a.delta);
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const int ob = (a.E * 12 + 255) / 256;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_learned_out<double>, dim3(ob), dim3(256), 0, s, static_cast<const double *>(a.q),
+                       static_cast<const double *>(a.q0), static_cast<const double *>(a.L1), a.C, a.delta, a.E,
+                       a.combine, a.c0, a.c1, a.dt, static_cast<double *>(a.out));
+  else
+    hipLaunchKernelGGL(k_learned_out<float>, dim3(ob), dim3(256), 0, s, static_cast<const float *>(a.q),
+                       static_cast<const float *>(a.q0), static_cast<const float *>(a.L1), a.C, a.delta, a.E,
+                       a.combine, (float)a.c0, (float)a.c1, (float)a.dt, static_cast<float *>(a.out));
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ projection
+// Cos-weighted L2 projection of an order-r state onto order 1 on the same
+// mesh: the longitude degrees a <= 1 are kept (orthonormal), the latitude
+// degrees mix through the per-row 2 x (r+1) matrix Pj[b'][b].
+template <typename T>
+__global__ void k_project1(const T *__restrict__ q, int n_lon, int E, int np, const double *__restrict__ P,
+                           T *__restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= E * 12) return;
+  const int e = idx / 12, k = idx - e * 12;
+  const int v = k / 4, m = k - v * 4, a = m & 1, bp = m >> 1;
+  const int j = e / n_lon;
+  const T *qe = q + (size_t)e * 3 * np * np + (size_t)v * np * np;
+  double acc = 0.0;
+  if (a < np)
+    for (int b = 0; b < np; ++b) acc += P[((size_t)j * 2 + bp) * np + b] * (double)qe[b * np + a];
+  out[idx] = (T)acc;
+}
+
+hipError_t launch_project1(int dtype, const void *q, int n_lon, int E, int np, const double *P, void *out,
+                           hipStream_t s) {
+  const int blocks = (E * 12 + 255) / 256;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_project1<double>, dim3(blocks), dim3(256), 0, s, static_cast<const double *>(q), n_lon, E, np,
+                       P, static_cast<double *>(out));
+  else
+    hipLaunchKernelGGL(k_project1<float>, dim3(blocks), dim3(256), 0, s, static_cast<const float *>(q), n_lon, E, np,
+                       P, static_cast<float *>(out));
+  return hipGetLastError();
+}
+
+}  // namespace dgsw

@@ -1,0 +1,64 @@
+// Launchers of the learned-correction kernels (dgsw_mlp.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dgsw {
+
+constexpr int kFeatures = 108;   // 3 x 3 stencil x 3 variables x 4 modes
+constexpr int kHidden = 256;
+constexpr int kOut = 12;         // 3 variables x 4 modes of r = 1
+constexpr int kInPad = 128;      // feature width padded for the K loop
+constexpr int kOutPad = 32;      // output width padded for the N tiles
+
+enum { kEpiBiasGelu = 0, kEpiBias = 1, kEpiGeluGrad = 2, kEpiPlain = 3 };
+
+struct GemmArgs {
+  const __bf16 *A, *B;
+  int M, N, K, lda, ldb;
+  const float *bias;   // kEpiBiasGelu, kEpiBias
+  const float *Zin;    // kEpiGeluGrad: pre-activations
+  float *Zout;         // kEpiBiasGelu: pre-activations out; kEpiGeluGrad: FP32 result out (optional)
+  void *C;             // BF16 (gelu variants) or FP32 result
+  int ldc;
+};
+hipError_t launch_gemm(bool a_kc, bool b_kc, int epi, const GemmArgs &g, hipStream_t s);
+hipError_t launch_prep_weights(const float *W, int k_in, int n_out, int kp, int np_, __bf16 *Wt, __bf16 *Wr,
+                               hipStream_t s);
+hipError_t launch_mse_grad(const float *Y, const float *T, const float *mask, int rows, int n_out, int ld, float scale,
+                           __bf16 *dY, float *dYf, float *partial, int *nblocks, hipStream_t s);
+hipError_t launch_colsum(const float *G, int rows, int n, int ld, float *out, hipStream_t s);
+hipError_t launch_sum(const float *p, int n, float scale, float *out, hipStream_t s);
+hipError_t launch_to_bf16(const float *X, int rows, int n, int ldx, __bf16 *Xb, hipStream_t s);
+hipError_t launch_pad(const float *b, int n, int np_, float *out, hipStream_t s);
+hipError_t launch_unpad(const float *G, int k_in, int n_out, int np_, float *out, hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s);
+hipError_t launch_features(int dtype, const void *q, int n_lon, int n_lat, const float *mean, const float *istd,
+                           int ldx, __bf16 *X, hipStream_t s);
+hipError_t launch_features_f32(int dtype, const void *q, int n_lon, int n_lat, const float *mean, const float *istd,
+                               float *X, hipStream_t s);
+hipError_t launch_project1(int dtype, const void *q, int n_lon, int E, int np, const double *P, void *out,
+                           hipStream_t s);
+
+struct LearnedLaunch {
+  const float *Y;        // network output, [E][ldy] standardised
+  int ldy;
+  const void *L1;        // plain r = 1 right-hand side [E][12]
+  const float *omean, *ostd;   // [n_lat][12]
+  const double *mass_w;  // [n_lat][2]
+  int n_lon, E;
+  float kappa;
+  float *C;              // corrections [E][12]
+  double *partial;       // ceil(E / 256)
+  int *fallback;         // optional device counter
+  double area;           // sum over elements of mass_w[j][0]
+  float *delta;          // device scalar
+  const void *q, *q0;
+  void *out;
+  int combine;
+  double c0, c1, dt;
+};
+hipError_t launch_correction(int dtype, const LearnedLaunch &a, hipStream_t s);
+
+}  // namespace dgsw

@@ -1,0 +1,229 @@
+"""The learned correction's kernels against the NumPy oracle: network forward
+and gradients (same BF16 rounding points), Adam, stencil features, the
+projection onto order 1, and the learned right-hand side's fallback and
+mass conservation."""
+import sys
+
+import numpy as np
+import pytest
+
+from dg_inputs import band_limited_state
+from oracle import SphereDG, mlp, project_order
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_11767_amd as dg
+    from paper_2303_11767_amd import learned
+    return dg, learned
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def flat(p):
+    return np.concatenate([p[k].reshape(-1) for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def unflat(v):
+    sizes = [("W1", (108, 256)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
+             ("W3", (256, 12)), ("b3", (12,))]
+    out, o = {}, 0
+    for k, shp in sizes:
+        n = int(np.prod(shp))
+        out[k] = v[o:o + n].reshape(shp)
+        o += n
+    return out
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def make_params(seed):
+    p = mlp.init_params(seed)
+    rng = np.random.default_rng(seed + 1)
+    for k in ("b1", "b2", "b3"):
+        p[k] = 0.1 * rng.standard_normal(p[k].shape)
+    # round to FP32 so both sides start from the same numbers
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+
+
+def test_param_count(dg):
+    _, learned = dg
+    assert learned.param_count() == 108 * 256 + 256 + 256 * 256 + 256 + 256 * 12 + 12
+
+
+@pytest.mark.parametrize("rows", [1, 37, 256, 1000])
+def test_forward_matches_oracle(dg, rows):
+    _, learned = dg
+    say("mlp forward", rows)
+    p = make_params(3)
+    X = np.random.default_rng(rows).standard_normal((rows, 108)).astype(np.float32).astype(np.float64)
+    Y = learned.mlp_forward(dev(flat(p)), dev(X)).cpu().numpy()
+    ref, _ = mlp.forward(p, X)
+    err = rel(Y, ref)
+    say("  normwise", err)
+    # BF16 rounding of the hidden activations is decided on FP32 sums in the
+    # kernel and FP64 sums in the oracle: values within accumulation error of a
+    # rounding boundary (about 1 in 4000) round to neighbouring BF16 numbers,
+    # 2^-8 apart, which moves the outputs by about 1e-4 normwise
+    assert err <= 3e-4
+
+
+@pytest.mark.parametrize("rows", [32, 256])
+def test_gradients_match_oracle(dg, rows):
+    _, learned = dg
+    say("mlp gradients", rows)
+    p = make_params(5)
+    rng = np.random.default_rng(10 + rows)
+    X = rng.standard_normal((rows, 108)).astype(np.float32).astype(np.float64)
+    T = rng.standard_normal((rows, 12)).astype(np.float32).astype(np.float64)
+    mask = np.ones(12)
+    mask[0] = 0.0
+    P = learned.param_count()
+    grads = torch.zeros(P, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    learned.mlp_train_step(dev(flat(p)), dev(X), dev(T), dev(mask), grads=grads, loss=loss)
+    Y, cache = mlp.forward(p, X)
+    g = mlp.backward(p, cache, Y, T, mask)
+    assert abs(loss.item() - mlp.loss(Y, T, mask)) <= 1e-4 * mlp.loss(Y, T, mask)
+    gg = unflat(grads.cpu().numpy().astype(np.float64))
+    for k in g:
+        err = rel(gg[k], g[k])
+        say("  grad", k, err)
+        assert err <= 1e-3, k
+
+
+def test_adam_step_matches_oracle(dg):
+    _, learned = dg
+    say("adam")
+    p = make_params(7)
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((64, 108)).astype(np.float32).astype(np.float64)
+    T = rng.standard_normal((64, 12)).astype(np.float32).astype(np.float64)
+    mask = np.ones(12)
+    P = learned.param_count()
+    pd = dev(flat(p))
+    m = torch.zeros(P, dtype=torch.float32, device="cuda")
+    v = torch.zeros(P, dtype=torch.float32, device="cuda")
+    grads = torch.zeros(P, dtype=torch.float32, device="cuda")
+    state = {}
+    for step in (1, 2, 3):
+        learned.mlp_train_step(pd, dev(X), dev(T), dev(mask), m, v, step, 1e-3, grads=grads)
+        mlp.adam(p, unflat(grads.cpu().numpy().astype(np.float64)), state)
+    err = np.abs(pd.cpu().numpy() - flat(p)).max()
+    say("  max param difference after 3 steps", err)
+    assert err <= 1e-5
+
+
+def test_training_reduces_loss(dg):
+    """200 Adam steps on a smooth synthetic regression shrink the loss."""
+    _, learned = dg
+    say("training")
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((108, 12)) / np.sqrt(108)
+    X = rng.standard_normal((4096, 108))
+    T = np.tanh(X @ A)
+    p = make_params(12)
+    P = learned.param_count()
+    pd = dev(flat(p))
+    m = torch.zeros(P, dtype=torch.float32, device="cuda")
+    v = torch.zeros(P, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    Xd, Td, md = dev(X), dev(T), dev(np.ones(12))
+    learned.mlp_train_step(pd, Xd, Td, md, loss=loss)
+    l0 = loss.item()
+    for step in range(1, 201):
+        learned.mlp_train_step(pd, Xd, Td, md, m, v, step, 1e-3, loss=loss)
+    say("  loss", l0, "->", loss.item())
+    assert loss.item() < 0.2 * l0
+
+
+def test_features_and_projection_match_oracle(dg):
+    dgm, learned = dg
+    say("features, projection")
+    n_lon, n_lat = 20, 10
+    for dtype in ("f64", "f32"):
+        m4 = dgm.Mesh(n_lon, n_lat, 4, dtype=dtype)
+        m1 = dgm.Mesh(n_lon, n_lat, 1, dtype=dtype)
+        q4, _ = band_limited_state(n_lon, n_lat, 4, 6, 21)
+        td = torch.float64 if dtype == "f64" else torch.float32
+        q4d = torch.from_numpy(q4).to("cuda", td)
+        q1 = learned.project(m4, m1, q4d).cpu().numpy()
+        ref = project_order(q4d.cpu().numpy().astype(np.float64), SphereDG(n_lon, n_lat, 4),
+                            SphereDG(n_lon, n_lat, 1))
+        tol = 1e-13 if dtype == "f64" else 1e-6
+        assert np.abs(q1 - ref).max() <= tol * np.abs(ref).max()
+        X = learned.features(m1, torch.from_numpy(q1).to("cuda", td)).cpu().numpy()
+        np.testing.assert_allclose(X, mlp.stencil_features(q1, n_lon, n_lat), rtol=1e-6, atol=0)
+
+
+def _learned_setup(dg, kappa, params=None, dtype="f64"):
+    dgm, learned = dg
+    n_lon, n_lat = 36, 18
+    mesh = dgm.Mesh(n_lon, n_lat, 1, dtype=dtype, h_ref=1e4 if dtype == "f32" else 0.0)
+    q, _ = band_limited_state(n_lon, n_lat, 1, 6, 31)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    qd = torch.from_numpy(q).to("cuda", td)
+    P = learned.param_count()
+    if params is None:
+        params = dev(flat(make_params(9)) * 0.1)
+    X = learned.features(mesh, qd)
+    fmean = X.mean(0).contiguous()
+    fistd = (1.0 / (X.std(0) + 1e-6)).contiguous()
+    L = mesh.rhs(qd).to(torch.float32).view(n_lat, n_lon, 12)
+    omean = torch.zeros((n_lat, 12), dtype=torch.float32, device="cuda")
+    ostd = (L.abs().amax(1) * 0.05).contiguous()
+    net = learned.LearnedRHS(mesh, params, fmean, fistd, omean, ostd, kappa=kappa)
+    return mesh, qd, net
+
+
+def test_learned_rhs_fallback_and_mass(dg):
+    """kappa = 0 or a non-finite network: every element falls back and the
+    learned right-hand side equals the plain one bitwise; with a finite
+    network the correction keeps the total h-mass tendency at roundoff."""
+    say("learned fallback")
+    mesh, q, net = _learned_setup(dg, kappa=0.0)
+    plain = mesh.rhs(q)
+    out = net.rhs(q)
+    assert torch.equal(out, plain)
+    assert net.fallbacks.item() == mesh.E
+    bad = torch.full((dg[1].param_count(),), float("nan"), dtype=torch.float32, device="cuda")
+    mesh2, q2, net2 = _learned_setup(dg, kappa=1e30, params=bad)
+    assert torch.equal(net2.rhs(q2), mesh2.rhs(q2))
+    assert net2.fallbacks.item() == mesh2.E
+    mesh3, q3, net3 = _learned_setup(dg, kappa=1e30)
+    out3 = net3.rhs(q3)
+    assert net3.fallbacks.item() == 0
+    diff = (out3 - mesh3.rhs(q3)).abs().max().item()
+    assert diff > 0
+    m_plain = mesh3.mass(mesh3.rhs(q3))[0]
+    m_learn = mesh3.mass(out3)[0]
+    scale = mesh3.mass(q3)[0] / 3600.0
+    say("  h-mass tendency plain", m_plain, "learned", m_learn, "scale", scale)
+    assert abs(m_learn - m_plain) <= 1e-9 * scale
+
+
+def test_learned_rk_step_runs(dg):
+    say("learned rk step")
+    dgm, learned = dg
+    for dtype in ("f64", "f32"):
+        mesh, q, net = _learned_setup(dg, kappa=1.0, dtype=dtype)
+        m0 = mesh.mass(q)[0]
+        dt = dgm.cfl_time_step(mesh, 334.0, 0.1)
+        net.rk_step(q, mesh.empty_work(), dt, nsteps=10)
+        m1 = mesh.mass(q)[0]
+        assert np.isfinite(m1)
+        assert abs(m1 - m0) <= (1e-13 if dtype == "f64" else 1e-6) * abs(m0)
