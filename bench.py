@@ -31,6 +31,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "DG RHS DOF-updates/s + % HBM roofline; learned r=1 vs plain r=4 at equal err"
 COUNTERS = os.path.join(ROOT, "profiles", "k_dg_stage_r3_180x90_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2303_11767_amd", "csrc", "dgsw_kernels.hip")
+LEARNED_MODEL = os.path.join(ROOT, "paper_2303_11767_amd", "models", "learned_r1_360x180.npz")
 
 
 def kernel_sha():
@@ -171,6 +172,74 @@ def run(args):
     return out
 
 
+def ensemble_section(steps=10):
+    """64 members of uneven order (r in 2..4) and resolution (90x45 to
+    360x180), FP32: the batched launches (autotuned schedule, graph replay)
+    against one plain launch sequence per member, same GPU, same steps."""
+    import torch
+
+    import paper_2303_11767_amd as dg
+    from dg_inputs import band_limited_state, ensemble_members
+    mem = ensemble_members(64, seed=4)
+    ens = dg.Ensemble(mem, dtype="f32", h_ref=1e4)
+    q = ens.empty_state()
+    work = ens.empty_work()
+    dts = []
+    for k, (m, v) in enumerate(zip(ens.members, ens.views(q))):
+        qh, info = band_limited_state(m.n_lon, m.n_lat, m.order, 16, mem[k]["seed"])
+        v.copy_(torch.from_numpy(qh).to(v.dtype))
+        dts.append(dg.cfl_time_step(m, info.cmax, 0.1))
+    ens.set_dt(dts)
+    dofs = sum(m.state_size() for m in ens.members)
+    schedule = ens.autotune(q, work)
+
+    def timed(fn):
+        fn(2)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn(steps)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3 / steps
+
+    t_ens = timed(lambda n: ens.rk_step(q, work, nsteps=n))
+    g = ens.graph(q, work, nsteps=steps)
+    t_graph = timed(lambda n: g.launch())
+    g.close()
+    ens.set_schedule(schedule[0], schedule[1], True)
+    t_fused = timed(lambda n: ens.rk_step(q, work, nsteps=n))
+    ens.set_schedule(*schedule)
+    views = ens.views(q)
+    works = [m.empty_work() for m in ens.members]
+
+    def plain(n):
+        for _ in range(n):
+            for k, m in enumerate(ens.members):
+                m.rk_step(views[k], works[k], dts[k], nsteps=1)
+
+    t_plain = timed(plain)
+    state_bytes = dofs * 4
+    return {"members": 64, "dofs": dofs, "dtype": "f32", "state_bytes": state_bytes,
+            "schedule": {"waves_per_group": schedule[0], "groups": schedule[1],
+                         "fused": schedule[2]},
+            "ms_per_step": {"batched": t_ens * 1e3, "batched_graph": t_graph * 1e3,
+                            "fused_single_launch": t_fused * 1e3, "plain_per_member": t_plain * 1e3},
+            "dof_updates_per_s": {"batched": 3 * dofs / t_ens, "plain_per_member": 3 * dofs / t_plain},
+            "alg_GBs_batched": 8 * state_bytes / t_ens / 1e9}
+
+
+def learned_section(model_path, seeds=(200, 201), t_eval=10.0):
+    """The learned r = 1 form against plain r = 1 and plain r = 4, judged by
+    the plain r = 5 solver (FP64, held-out seeds), with wall-clock."""
+    import argparse as _ap
+    from paper_2303_11767_amd import train_learned as tl
+    model, meta = tl.load_model(model_path)
+    rep = tl.judge(_ap.Namespace(kappa=meta.get("kappa", 1.0)), model, seeds, t_eval)
+    rep["model"] = os.path.relpath(model_path, ROOT)
+    return rep
+
+
 def profile_probe(args):
     """Short run for rocprofv3 counter passes: a few 3-stage cycles of the
     stage kernel, then device-to-device copies of a known size (the
@@ -206,19 +275,24 @@ def main():
     ap.add_argument("--kernel-cycles", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the ensemble and learned-correction sections")
     ap.add_argument("--profile-probe", action="store_true",
                     help="short run for rocprofv3 counter passes (prints no bench line)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build runs the DG loop on a single device "
-              "(multi-GPU sharding is a design note, not an implemented path); use --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the DG loop runs on a single device "
+              "(sharding across GPUs is not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.profile_probe:
         profile_probe(args)
         return
     out = run(args)
+    if not args.no_extras:
+        out["ensemble"] = ensemble_section()
+        if os.path.exists(LEARNED_MODEL):
+            out["learned"] = learned_section(LEARNED_MODEL)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -62,8 +62,10 @@ enum { DG_METRIC_BALANCED = 0, DG_METRIC_POINTWISE = 1 };
 enum { DG_ALPHA_LOCAL = 0, DG_ALPHA_GLOBAL = 1 };
 
 /* Runge-Kutta schemes of Table "Butcher": RK1 (forward Euler), RK2 (Heun),
- * RK3 (the third tableau, SSP), each applied in Shu-Osher form. */
-enum { DG_SSP_RK1 = 1, DG_SSP_RK2 = 2, DG_SSP_RK3 = 3 };
+ * RK3 (the third tableau, SSP), each applied in Shu-Osher form, and the
+ * classical four-stage RK4 (the fourth tableau, the scheme of the spherical
+ * runs of Sec. 4.3-4.4; not SSP). */
+enum { DG_SSP_RK1 = 1, DG_SSP_RK2 = 2, DG_SSP_RK3 = 3, DG_RK4 = 4 };
 
 enum {
   DG_OK = 0,
@@ -110,7 +112,7 @@ int dg_free(dg_ctx *ctx);
 int dg_state_size(const dg_ctx *ctx, int64_t *n_values);
 
 /* Number of scalars the `work` argument of dg_rk_step must hold for the
- * scheme (2 state buffers for RK2/RK3, 1 for RK1). */
+ * scheme (1 state buffer for RK1, 2 for RK2/RK3, 3 for RK4). */
 int dg_work_size(const dg_ctx *ctx, int32_t scheme, int64_t *n_values);
 
 /* Smallest element width [m] for the Courant number p c dt / H of section 2
@@ -126,8 +128,11 @@ int dg_rhs(dg_ctx *ctx, const void *q, void *dqdt, void *hip_stream);
 
 /* Advance q in place by nsteps >= 0 steps of size dt of the scheme (Shu-Osher
  * form; for RK3: q1 = q + dt L(q); q2 = 3/4 q + 1/4 (q1 + dt L(q1));
- * q <- 1/3 q + 2/3 (q2 + dt L(q2))).  work: dg_work_size scalars of scratch,
- * not overlapping q; its contents are undefined afterwards. */
+ * q <- 1/3 q + 2/3 (q2 + dt L(q2)).  RK4: q1 = q + dt/2 L(q);
+ * q2 = q + dt/2 L(q1); q3 = q + dt L(q2);
+ * q <- (q1 + 2 q2 + q3 - q)/3 + dt/6 L(q3), which equals the fourth tableau.)
+ * work: dg_work_size scalars of scratch, not overlapping q; its contents are
+ * undefined afterwards. */
 int dg_rk_step(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme,
                int32_t nsteps, void *hip_stream);
 

@@ -9,11 +9,11 @@ import ctypes
 import math
 
 from ._lib import (DG_ALPHA_GLOBAL, DG_ALPHA_LOCAL, DG_F32, DG_F64, DG_METRIC_BALANCED,
-                   DG_METRIC_POINTWISE, DG_SSP_RK1, DG_SSP_RK2, DG_SSP_RK3, DGError,
+                   DG_METRIC_POINTWISE, DG_SSP_RK1, DG_SSP_RK2, DG_SSP_RK3, DG_RK4, DGError,
                    MeshDesc, check, load)
 
 __all__ = ["Mesh", "Ensemble", "Graph", "DGError", "cfl_time_step", "DG_SSP_RK1", "DG_SSP_RK2",
-           "DG_SSP_RK3"]
+           "DG_SSP_RK3", "DG_RK4"]
 
 RADIUS, GRAVITY, OMEGA = 6.371e6, 9.80616, 7.292e-5
 

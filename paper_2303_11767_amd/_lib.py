@@ -13,7 +13,7 @@ DG_ABI_VERSION = 1
 DG_F64, DG_F32 = 0, 1
 DG_METRIC_BALANCED, DG_METRIC_POINTWISE = 0, 1
 DG_ALPHA_LOCAL, DG_ALPHA_GLOBAL = 0, 1
-DG_SSP_RK1, DG_SSP_RK2, DG_SSP_RK3 = 1, 2, 3
+DG_SSP_RK1, DG_SSP_RK2, DG_SSP_RK3, DG_RK4 = 1, 2, 3, 4
 DG_OK, DG_EINVAL, DG_EDTYPE, DG_ENOMEM, DG_EHIP, DG_ENONFINITE, DG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
 ERROR_NAMES = {

@@ -183,6 +183,7 @@ int dg_work_size(const dg_ctx *ctx, int32_t scheme, int64_t *n_values) {
     case DG_SSP_RK1: *n_values = ctx->state_n; return DG_OK;
     case DG_SSP_RK2:
     case DG_SSP_RK3: *n_values = 2 * ctx->state_n; return DG_OK;
+    case DG_RK4: *n_values = 3 * ctx->state_n; return DG_OK;
     default: return fail(DG_EINVAL, "unknown scheme");
   }
 }
@@ -211,6 +212,35 @@ static int stage(dg_ctx *c, const void *q, const void *q0, void *out, int combin
   a.c0 = c0;
   a.c1 = c1;
   a.dt = dt;
+  hipError_t e = dgsw::launch_stage(c->d.dtype == DG_F64 ? 0 : 1, c->np, a, s);
+  if (e != hipSuccess) return hip_fail(e, "stage kernel launch");
+  return DG_OK;
+}
+
+// General stage: out = c0 q0 + c1 q + dt L(q) + ca qa + cb qb (qa, qb, q0 read
+// at the element itself only, so any of them may be the same buffer as out).
+static int stage_general(dg_ctx *c, const void *q, const void *q0, void *out, double c0,
+                         double c1, double dt, const void *qa, double ca, const void *qb,
+                         double cb, hipStream_t s) {
+  dgsw::StageLaunch a;
+  a.q = q;
+  a.q0 = q0;
+  a.out = out;
+  a.forcing = c->forcing;
+  a.glob = c->d_glob;
+  a.rows = c->d_rows;
+  a.n_lon = c->d.n_lon;
+  a.n_lat = c->d.n_lat;
+  a.E = c->E;
+  a.alpha_global = c->d.alpha_mode == DG_ALPHA_GLOBAL;
+  a.combine = 2;
+  a.c0 = c0;
+  a.c1 = c1;
+  a.dt = dt;
+  a.qa = qa;
+  a.qb = qb;
+  a.ca = ca;
+  a.cb = cb;
   hipError_t e = dgsw::launch_stage(c->d.dtype == DG_F64 ? 0 : 1, c->np, a, s);
   if (e != hipSuccess) return hip_fail(e, "stage kernel launch");
   return DG_OK;
@@ -262,6 +292,20 @@ int dg_rk_step(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme, int3
         if ((rc = stage(ctx, w0, q, w1, 1, 0.75, 0.25, dt, s)) != DG_OK) return rc;
         if ((rc = stage(ctx, w1, q, q, 1, 1.0 / 3.0, 2.0 / 3.0, dt, s)) != DG_OK) return rc;
         break;
+      case DG_RK4: {
+        char *w2 = w1 + bytes;
+        if ((rc = stage(ctx, q, nullptr, w0, 1, 0.0, 1.0, 0.5 * dt, s)) != DG_OK) return rc;
+        if ((rc = stage_general(ctx, w0, q, w1, 1.0, 0.0, 0.5 * dt, nullptr, 0.0, nullptr, 0.0,
+                                s)) != DG_OK)
+          return rc;
+        if ((rc = stage_general(ctx, w1, q, w2, 1.0, 0.0, dt, nullptr, 0.0, nullptr, 0.0, s)) !=
+            DG_OK)
+          return rc;
+        if ((rc = stage_general(ctx, w2, q, q, -1.0 / 3.0, 1.0 / 3.0, dt / 6.0, w0, 1.0 / 3.0, w1,
+                                2.0 / 3.0, s)) != DG_OK)
+          return rc;
+        break;
+      }
       default:
         return fail(DG_EINVAL, "unknown scheme");
     }

@@ -51,8 +51,11 @@ struct StageLaunch {
   const void *rows;     // RowTab<T, NP>[n_lat] on the device
   int n_lon, n_lat, E;
   int alpha_global;
-  int combine;          // 0: out = L(q); 1: out = c0 q0 + c1 (q + dt L(q))
+  int combine;          // 0: out = L(q); 1: out = c0 q0 + c1 (q + dt L(q));
+                        // 2: out = c0 q0 + c1 q + dt L(q) + ca qa + cb qb
   double c0, c1, dt;
+  const void *qa = nullptr, *qb = nullptr;   // extra operands of combine == 2
+  double ca = 0.0, cb = 0.0;
 };
 
 // dtype 0 = double, 1 = float; np = order + 1.  Returns a hipError_t.

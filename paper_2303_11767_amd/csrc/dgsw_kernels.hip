@@ -24,8 +24,10 @@
 //   xi pass   lane t = latitude degree b: contraction over the longitude nodes
 //             with P~' (F term) and P~ (G and S terms), east/west surface
 //             terms, giving row b of dq/dt = M^-1 h(q) (eq. "ode")
-//   epilogue  optional forcing, then either dq/dt or the Shu-Osher stage
-//             combination c0 q^n + c1 (q + dt dq/dt), stored as row b.
+//   epilogue  optional forcing, then either dq/dt, the Shu-Osher stage
+//             combination c0 q^n + c1 (q + dt dq/dt), or the general one
+//             c0 q^n + c1 q + dt dq/dt + ca qa + cb qb (classical RK4), stored
+//             as row b.
 //
 // The weak form is that of eq. "dg_parts": volume term of F . grad(phi) plus
 // the source, minus the surface term of the Rusanov flux times phi.  Integrals
@@ -179,10 +181,11 @@ struct StageArgs {
   const T *q0;           // q^n of the combination (may alias out)
   T *out;
   const T *forcing;      // optional modal forcing
+  const T *qa, *qb;      // extra states of the general combination (may be null)
   const GlobTab<T, NP> *gt;
   const RowTab<T, NP> *rows;
   int n_lon, n_lat, alpha_global, combine;
-  T c0, c1, dt;
+  T c0, c1, dt, ca, cb;
 };
 
 // One wavefront's share of a stage: GPW elements of one latitude row
@@ -435,6 +438,13 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
       XE += S[6 * NP * NP + (v * 2 + 0) * NP + p] * bmt[p];
       XW += S[6 * NP * NP + (v * 2 + 1) * NP + p] * bmt[p];
     }
+    // general combination (combine == 2, classical RK4): its two extra
+    // operands, loaded one variable at a time
+    T xa[NP], xb[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) xa[a] = xb[a] = T(0);
+    if (combine == 2 && A.qa) load_row<T, NP>(A.qa + base + v * N, xa);
+    if (combine == 2 && A.qb) load_row<T, NP>(A.qb + base + v * N, xb);
     T res[NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
@@ -443,7 +453,10 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
       for (int p = 0; p < NP; ++p) acc += gt->D[p][a] * zd[p] + gt->B[p][a] * zb[p];
       acc -= cF * (gt->Pp[a] * XE - gt->Pm[a] * XW);
       acc += fr[v][a];
-      res[a] = combine ? c0 * q0r[v][a] + c1 * (qr[v][a] + dt * acc) : acc;
+      if (combine == 2)
+        res[a] = c0 * q0r[v][a] + c1 * qr[v][a] + dt * acc + A.ca * xa[a] + A.cb * xb[a];
+      else
+        res[a] = combine ? c0 * q0r[v][a] + c1 * (qr[v][a] + dt * acc) : acc;
     }
     if (active) store_row<T, NP>(out + base + v * N, res);
   }
@@ -496,6 +509,8 @@ __device__ __forceinline__ void ens_case(const EnsItem &m, const T *q, const T *
   A.q0 = q0 ? q0 + m.off : nullptr;
   A.out = out + m.off;
   A.forcing = nullptr;
+  A.qa = A.qb = nullptr;
+  A.ca = A.cb = T(0);
   A.gt = static_cast<const GlobTab<T, NP> *>(m.glob);
   A.rows = static_cast<const RowTab<T, NP> *>(m.rows);
   A.n_lon = m.n_lon;
@@ -710,6 +725,10 @@ static StageArgs<T, NP> stage_args(const StageLaunch &a) {
   A.q0 = static_cast<const T *>(a.q0);
   A.out = static_cast<T *>(a.out);
   A.forcing = static_cast<const T *>(a.forcing);
+  A.qa = static_cast<const T *>(a.qa);
+  A.qb = static_cast<const T *>(a.qb);
+  A.ca = T(a.ca);
+  A.cb = T(a.cb);
   A.gt = static_cast<const GlobTab<T, NP> *>(a.glob);
   A.rows = static_cast<const RowTab<T, NP> *>(a.rows);
   A.n_lon = a.n_lon;

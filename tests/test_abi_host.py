@@ -21,6 +21,19 @@ def test_header_and_binding_agree():
     assert header_functions() == sorted(_lib.EXPORTS)
 
 
+def test_header_constants_match_binding():
+    """Every enumerator the header defines has the same value in the binding."""
+    src = open(HEADER).read()
+    found = 0
+    for body in re.findall(r"enum\s*\{([^}]*)\}", src):
+        for name, val in re.findall(r"(DG_\w+)\s*=\s*(-?\d+)", body):
+            if hasattr(_lib, name):
+                assert getattr(_lib, name) == int(val), name
+                found += 1
+    assert found >= 10
+    assert _lib.DG_RK4 == 4
+
+
 def test_library_exports_every_declared_symbol():
     lib = _lib.load()
     for name in header_functions():

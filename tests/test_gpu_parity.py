@@ -195,8 +195,10 @@ def test_rk3_c1_100_steps(dg):
     np.testing.assert_allclose(m1, m.mass(got), rtol=1e-13)
 
 
-@pytest.mark.parametrize("scheme,name", [(1, "RK1"), (2, "RK2")])
-def test_rk1_rk2_match_printed_tableaux(dg, scheme, name):
+@pytest.mark.parametrize("scheme,name", [(1, "RK1"), (2, "RK2"), (4, "RK4")])
+def test_rk_schemes_match_printed_tableaux(dg, scheme, name):
+    """One step of RK1, RK2 and the classical RK4 (the library's low-storage
+    combination) against the printed tableau applied literally."""
     import json
     say("rk", name)
     tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "butcher_tableaux.json")))[name]
@@ -210,6 +212,48 @@ def test_rk1_rk2_match_printed_tableaux(dg, scheme, name):
     got = qd.cpu().numpy()
     bound = 1e-12 * dt * m.rhs_scale(q) + 4e-16 * np.abs(q)
     assert np.all(np.abs(got - ref) <= 4 * bound)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_rk4_trajectory_and_graph(dg, dtype):
+    """40 classical RK4 steps at 32 x 16, r = 2 against the oracle's literal
+    tableau steps; h-mass conserved; a captured graph of the same steps,
+    replayed three times, matches the eager launches bit for bit."""
+    import json
+    say("rk4 trajectory", dtype)
+    tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "butcher_tableaux.json")))["RK4"]
+    q, info = band_limited_state(32, 16, 2, 6, 52)
+    m = SphereDG(32, 16, 2)
+    dt = m.cfl_time_step(info.cmax, 0.1)
+    q_in = oracle_input(q, dtype)
+    ref = q_in.copy()
+    for _ in range(40):
+        ref = butcher_step(m.rhs, ref, dt, tab["A"], tab["b"])
+    mesh = make(dg, 32, 16, 2, dtype)
+    qd = to_dev(q, dtype)
+    work = mesh.empty_work(dg.DG_RK4)
+    m0 = mesh.mass(qd)
+    mesh.rk_step(qd, work, dt, scheme=dg.DG_RK4, nsteps=40)
+    got = qd.cpu().numpy().astype(np.float64)
+    rel = np.abs(got - ref).max(axis=(0, 2)) / np.abs(ref).max(axis=(0, 2))
+    say("  trajectory relative difference after 40 steps", rel)
+    assert np.all(rel < (1e-10 if dtype == "f64" else 2e-5))
+    m1 = mesh.mass(qd)
+    assert abs(m1[0] - m0[0]) <= (1e-13 if dtype == "f64" else 1e-6) * abs(m0[0])
+    # graph replays against the eager result
+    q_eager = to_dev(q, dtype)
+    mesh.rk_step(q_eager, work, dt, scheme=dg.DG_RK4, nsteps=3)
+    q_graph = to_dev(q, dtype)
+    g = mesh.graph(q_graph, work, dt, scheme=dg.DG_RK4, nsteps=1)
+    torch.cuda.synchronize()
+    try:
+        for rep in range(3):
+            g.launch()
+            torch.cuda.synchronize()
+            say("  replay", rep)
+        assert torch.equal(q_graph, q_eager)
+    finally:
+        g.close()
 
 
 # ---------------------------------------------------------------- mass and failures
