@@ -15,6 +15,9 @@ Recipe (the same for every workload):
   (numpy's Legendre routines).  This is input synthesis only: any smooth
   state is a valid input to the operator.
 
+The planar Gaussian bump (``gaussian_bump_plane``) follows the same
+projection on the periodic rectangle.
+
 Layout: q[e][v][m], e = j*n_lon + i (j = 0 southernmost row, i = 0 at
 longitude 0), v in (h, hu, hv), m = b*n + a (a: longitude degree,
 b: latitude degree).
@@ -129,3 +132,27 @@ def ensemble_members(n_members=64, seed=4, orders=(2, 3, 4), n_lats=(45, 90, 135
         nt = int(rng.choice(n_lats))
         out.append({"n_lon": 2 * nt, "n_lat": nt, "order": r, "seed": seed * 1000 + k})
     return out
+
+
+def gaussian_bump_plane(nx, ny, order, lx, ly, h0=1000.0, h1=5.0, sigma_frac=1.0 / 20.0, nq=None):
+    """Fluid at rest on the periodic rectangle [0, lx] x [0, ly] with a
+    Gaussian bump h0 + h1 exp(-r^2 / (2 sigma^2)) at the centre, sigma =
+    sigma_frac lx: the geostrophic-adjustment start of section 4.2
+    (h0 = 1000 m, h1 = 5 m, sigma = L/20).  Projected unweighted onto the
+    orthonormal basis like the sphere states; layout q[e][v][m] with
+    e = j nx + i (i along x)."""
+    n = order + 1
+    nq = nq or (n + 6)
+    x, w = npleg.leggauss(nq)
+    dx, dy = lx / nx, ly / ny
+    xs = (np.arange(nx)[:, None] + 0.5 * (1.0 + x[None, :])) * dx      # [i, p]
+    ys = (np.arange(ny)[:, None] + 0.5 * (1.0 + x[None, :])) * dy      # [j, s]
+    sig = sigma_frac * lx
+    r2 = (xs.ravel()[None, :] - 0.5 * lx) ** 2 + (ys.ravel()[:, None] - 0.5 * ly) ** 2
+    h = (h0 + h1 * np.exp(-r2 / (2.0 * sig * sig))).reshape(ny, nq, nx, nq)   # [j, s, i, p]
+    Vx = _orthonormal_vander(order, x)
+    qh = np.einsum("jsip,s,p,pa,sb->jiba", h, w, w, Vx, Vx).reshape(ny * nx, n * n)
+    q = np.zeros((ny * nx, 3, n * n))
+    q[:, 0] = qh
+    return q
+
