@@ -156,3 +156,38 @@ def gaussian_bump_plane(nx, ny, order, lx, ly, h0=1000.0, h1=5.0, sigma_frac=1.0
     q[:, 0] = qh
     return q
 
+
+def random_plane_state(nx, ny, order, lx, ly, seed, h0=1000.0, dh=5.0, vel=2.0, kmax=3, nq=None):
+    """Seeded smooth state on the periodic rectangle: h = h0 + a random sum of
+    Fourier modes |kx|, |ky| <= kmax scaled to max |dh| = dh, and (u, v) a
+    mean flow plus random modes scaled to max speed vel; projected like
+    ``gaussian_bump_plane``."""
+    rng = np.random.default_rng(seed)
+    n = order + 1
+    nq = nq or (n + 6)
+    x, w = npleg.leggauss(nq)
+    dx, dy = lx / nx, ly / ny
+    X = ((np.arange(nx)[:, None] + 0.5 * (1.0 + x[None, :])) * dx).ravel()
+    Y = ((np.arange(ny)[:, None] + 0.5 * (1.0 + x[None, :])) * dy).ravel()
+    XX, YY = np.meshgrid(X, Y)                     # [y, x]
+
+    def field():
+        out = np.zeros_like(XX)
+        for kx in range(-kmax, kmax + 1):
+            for ky in range(0, kmax + 1):
+                if kx == 0 and ky == 0:
+                    continue
+                a, ph = rng.standard_normal(), rng.uniform(0, 2 * np.pi)
+                out += a * np.cos(2 * np.pi * (kx * XX / lx + ky * YY / ly) + ph)
+        return out / np.abs(out).max()
+
+    h = h0 + dh * field()
+    u = 0.5 + field()
+    v = -0.3 + field()
+    s_ = vel / np.sqrt(u * u + v * v).max()
+    u, v = u * s_, v * s_
+    f = np.stack([h, h * u, h * v]).reshape(3, ny, nq, nx, nq)
+    Vx = _orthonormal_vander(order, x)
+    q = np.einsum("vjsip,s,p,pa,sb->jivba", f, w, w, Vx, Vx)
+    return np.ascontiguousarray(q.reshape(ny * nx, 3, n * n))
+

@@ -104,6 +104,28 @@ typedef struct {
  * *out is a new context; on failure *out is NULL. */
 int dg_init_mesh(const dg_mesh_desc *desc, void *hip_stream, dg_ctx **out);
 
+/* The planar shallow-water system of section 4.2 on the doubly periodic
+ * rectangle [0, lx] x [0, ly] with nx x ny elements: F = (hu, hu u + g h^2/2,
+ * hu v), G = (hv, hv u, hv v + g h^2/2), S = (0, f hv, -f hu) with constant f
+ * (the f-plane), no metric terms.  Element e = j nx + i (i along x, j along
+ * y), modes as on the sphere (a: x degree, b: y degree).  Every other call
+ * (dg_rhs, dg_rk_step, dg_rk_stage, dg_mass, dg_set_forcing, dg_min_width,
+ * graphs) works on the context as on a sphere mesh; dg_mass integrates over
+ * the rectangle; the learned-correction calls reject it. */
+typedef struct {
+  int32_t abi_version;  /* must be DG_ABI_VERSION                                     */
+  int32_t nx, ny;       /* elements along x and y (both periodic), >= 1               */
+  int32_t order;        /* polynomial degree r in each direction, 0..7                */
+  int32_t dtype;        /* DG_F64 or DG_F32                                           */
+  int32_t alpha_mode;   /* DG_ALPHA_*                                                  */
+  double alpha;         /* [m/s], used iff alpha_mode == DG_ALPHA_GLOBAL, >= 0         */
+  double lx, ly;        /* domain lengths [m], > 0                                     */
+  double gravity;       /* g [m/s^2], > 0                                              */
+  double f;             /* Coriolis parameter [1/s], finite                            */
+  double h_ref;         /* reference depth H [m] >= 0, as in dg_mesh_desc              */
+} dg_plane_desc;
+int dg_init_plane(const dg_plane_desc *desc, void *hip_stream, dg_ctx **out);
+
 /* Release a context and its device tables.  NULL is accepted.  The caller
  * must make sure no enqueued work still uses the context. */
 int dg_free(dg_ctx *ctx);

@@ -8,12 +8,12 @@ on the caller's current torch stream.
 import ctypes
 import math
 
-from ._lib import (DG_ALPHA_GLOBAL, DG_ALPHA_LOCAL, DG_F32, DG_F64, DG_METRIC_BALANCED,
-                   DG_METRIC_POINTWISE, DG_SSP_RK1, DG_SSP_RK2, DG_SSP_RK3, DG_RK4, DGError,
-                   MeshDesc, check, load)
+from ._lib import (DG_ABI_VERSION, DG_ALPHA_GLOBAL, DG_ALPHA_LOCAL, DG_F32, DG_F64,
+                   DG_METRIC_BALANCED, DG_METRIC_POINTWISE, DG_SSP_RK1, DG_SSP_RK2, DG_SSP_RK3,
+                   DG_RK4, DGError, MeshDesc, PlaneDesc, check, load)
 
-__all__ = ["Mesh", "Ensemble", "Graph", "DGError", "cfl_time_step", "DG_SSP_RK1", "DG_SSP_RK2",
-           "DG_SSP_RK3", "DG_RK4"]
+__all__ = ["Mesh", "Plane", "Ensemble", "Graph", "DGError", "cfl_time_step", "DG_SSP_RK1",
+           "DG_SSP_RK2", "DG_SSP_RK3", "DG_RK4"]
 
 RADIUS, GRAVITY, OMEGA = 6.371e6, 9.80616, 7.292e-5
 
@@ -197,6 +197,29 @@ class Mesh:
         except Exception:
             pass
 
+
+
+class Plane(Mesh):
+    """The doubly periodic f-plane [0, lx] x [0, ly] (section 4.2): a dg_ctx
+    built by dg_init_plane; every Mesh method applies.  n_lon / n_lat are the
+    element counts along x / y."""
+
+    def __init__(self, nx, ny, order, lx, ly, dtype="f64", f=1.0e-4, gravity=9.81,
+                 alpha_mode="local", alpha=0.0, h_ref=0.0, stream=None):
+        self._lib = load()
+        d = PlaneDesc()
+        d.abi_version, d.nx, d.ny, d.order = DG_ABI_VERSION, int(nx), int(ny), int(order)
+        d.dtype = {"f64": DG_F64, "f32": DG_F32}[dtype]
+        d.alpha_mode = {"local": DG_ALPHA_LOCAL, "global": DG_ALPHA_GLOBAL}[alpha_mode]
+        d.alpha, d.lx, d.ly = float(alpha), float(lx), float(ly)
+        d.gravity, d.f, d.h_ref = float(gravity), float(f), float(h_ref)
+        ctx = ctypes.c_void_p()
+        check(self._lib.dg_init_plane(ctypes.byref(d), _stream_handle(stream), ctypes.byref(ctx)))
+        self.plane = d
+        md = MeshDesc()
+        md.abi_version, md.n_lon, md.n_lat, md.order, md.dtype = DG_ABI_VERSION, d.nx, d.ny, d.order, d.dtype
+        md.alpha_mode, md.alpha, md.radius, md.gravity, md.h_ref = d.alpha_mode, d.alpha, 1.0, d.gravity, d.h_ref
+        self._setup(md, ctx, owns=True)
 
 class Ensemble:
     """Independent meshes of different size and order advanced together: one

@@ -22,7 +22,7 @@ ERROR_NAMES = {
 }
 
 # every symbol include/dgsw.h declares
-EXPORTS = ("dg_init_mesh", "dg_free", "dg_state_size", "dg_work_size", "dg_min_width", "dg_rhs",
+EXPORTS = ("dg_init_mesh", "dg_init_plane", "dg_free", "dg_state_size", "dg_work_size", "dg_min_width", "dg_rhs",
            "dg_rk_stage", "dg_rk_step", "dg_mass", "dg_set_forcing", "dg_last_error",
            "dg_ens_init", "dg_ens_free", "dg_ens_state_size", "dg_ens_offsets", "dg_ens_member",
            "dg_ens_set_dt", "dg_ens_rhs", "dg_ens_rk_stage", "dg_ens_rk_step", "dg_ens_set_schedule",
@@ -54,6 +54,14 @@ class MeshDesc(ctypes.Structure):
                 ("h_ref", ctypes.c_double)]
 
 
+class PlaneDesc(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("alpha_mode", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("lx", ctypes.c_double), ("ly", ctypes.c_double),
+                ("gravity", ctypes.c_double), ("f", ctypes.c_double), ("h_ref", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -67,6 +75,7 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
     lib.dg_init_mesh.argtypes = [ctypes.POINTER(MeshDesc), vp, ctypes.POINTER(vp)]
+    lib.dg_init_plane.argtypes = [ctypes.POINTER(PlaneDesc), vp, ctypes.POINTER(vp)]
     lib.dg_free.argtypes = [vp]
     lib.dg_state_size.argtypes = [vp, i64p]
     lib.dg_work_size.argtypes = [vp, i32, i64p]

@@ -82,21 +82,15 @@ extern "C" {
 
 const char *dg_last_error(void) { return dgsw::last_error(); }
 
-int dg_init_mesh(const dg_mesh_desc *desc, void *hip_stream, dg_ctx **out) {
-  if (!out) return fail(DG_EINVAL, "out is NULL");
-  *out = nullptr;
-  int rc = validate(desc);
-  if (rc != DG_OK) return rc;
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+}  // extern "C"
 
-  dgsw::HostTables t;
-  const char *msg = "";
-  if (!dgsw::build_tables(desc->n_lon, desc->n_lat, desc->order,
-                          desc->metric == DG_METRIC_BALANCED ? 0 : 1, desc->radius, t, &msg))
-    return fail(DG_EINVAL, msg);
+namespace {
 
+// Context from validated parameters and the host tables of its geometry.
+int make_ctx(const dg_mesh_desc *desc, const dgsw::HostTables &t, hipStream_t s, dg_ctx **out) {
   dg_ctx *c = new dg_ctx();
   c->d = *desc;
+  c->periodic_y = t.periodic_y ? 1 : 0;
   c->np = desc->order + 1;
   c->N = c->np * c->np;
   c->E = desc->n_lon * desc->n_lat;
@@ -160,6 +154,56 @@ int dg_init_mesh(const dg_mesh_desc *desc, void *hip_stream, dg_ctx **out) {
   return DG_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int dg_init_mesh(const dg_mesh_desc *desc, void *hip_stream, dg_ctx **out) {
+  if (!out) return fail(DG_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(desc);
+  if (rc != DG_OK) return rc;
+  dgsw::HostTables t;
+  const char *msg = "";
+  if (!dgsw::build_tables(desc->n_lon, desc->n_lat, desc->order,
+                          desc->metric == DG_METRIC_BALANCED ? 0 : 1, desc->radius, desc->omega,
+                          t, &msg))
+    return fail(DG_EINVAL, msg);
+  return make_ctx(desc, t, static_cast<hipStream_t>(hip_stream), out);
+}
+
+int dg_init_plane(const dg_plane_desc *p, void *hip_stream, dg_ctx **out) {
+  if (!out) return fail(DG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p) return fail(DG_EINVAL, "desc is NULL");
+  if (p->abi_version != DG_ABI_VERSION) return fail(DG_EINVAL, "abi_version mismatch");
+  if (!(p->lx > 0.0) || !std::isfinite(p->lx) || !(p->ly > 0.0) || !std::isfinite(p->ly))
+    return fail(DG_EINVAL, "lx and ly must be > 0");
+  if (!std::isfinite(p->f)) return fail(DG_EINVAL, "f must be finite");
+  // the sphere descriptor with the plane's values: validated by the same rules
+  dg_mesh_desc d{};
+  d.abi_version = p->abi_version;
+  d.n_lon = p->nx;
+  d.n_lat = p->ny;
+  d.order = p->order;
+  d.dtype = p->dtype;
+  d.metric = DG_METRIC_BALANCED;
+  d.alpha_mode = p->alpha_mode;
+  d.reserved = 0;
+  d.alpha = p->alpha;
+  d.radius = 1.0;
+  d.gravity = p->gravity;
+  d.omega = 0.0;
+  d.h_ref = p->h_ref;
+  int rc = validate(&d);
+  if (rc != DG_OK) return rc;
+  dgsw::HostTables t;
+  const char *msg = "";
+  if (!dgsw::build_tables_plane(p->nx, p->ny, p->order, p->lx, p->ly, p->f, t, &msg))
+    return fail(DG_EINVAL, msg);
+  return make_ctx(&d, t, static_cast<hipStream_t>(hip_stream), out);
+}
+
 int dg_free(dg_ctx *ctx) {
   release(ctx);
   return DG_OK;
@@ -208,6 +252,7 @@ static int stage(dg_ctx *c, const void *q, const void *q0, void *out, int combin
   a.n_lat = c->d.n_lat;
   a.E = c->E;
   a.alpha_global = c->d.alpha_mode == DG_ALPHA_GLOBAL;
+  a.periodic_y = c->periodic_y;
   a.combine = combine;
   a.c0 = c0;
   a.c1 = c1;
@@ -217,11 +262,12 @@ static int stage(dg_ctx *c, const void *q, const void *q0, void *out, int combin
   return DG_OK;
 }
 
-// General stage: out = c0 q0 + c1 q + dt L(q) + ca qa + cb qb (qa, qb, q0 read
-// at the element itself only, so any of them may be the same buffer as out).
-static int stage_general(dg_ctx *c, const void *q, const void *q0, void *out, double c0,
-                         double c1, double dt, const void *qa, double ca, const void *qb,
-                         double cb, hipStream_t s) {
+// General stage: out = q0 + c1 (q - q0) + ca (qa - q0) + cb (qb - q0) + dt L(q)
+// (q0, qa, qb read at the element itself only, so any of them may be the same
+// buffer as out).
+static int stage_general(dg_ctx *c, const void *q, const void *q0, void *out, double c1,
+                         double dt, const void *qa, double ca, const void *qb, double cb,
+                         hipStream_t s) {
   dgsw::StageLaunch a;
   a.q = q;
   a.q0 = q0;
@@ -233,8 +279,9 @@ static int stage_general(dg_ctx *c, const void *q, const void *q0, void *out, do
   a.n_lat = c->d.n_lat;
   a.E = c->E;
   a.alpha_global = c->d.alpha_mode == DG_ALPHA_GLOBAL;
+  a.periodic_y = c->periodic_y;
   a.combine = 2;
-  a.c0 = c0;
+  a.c0 = 1.0 - c1 - ca - cb;
   a.c1 = c1;
   a.dt = dt;
   a.qa = qa;
@@ -295,14 +342,13 @@ int dg_rk_step(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme, int3
       case DG_RK4: {
         char *w2 = w1 + bytes;
         if ((rc = stage(ctx, q, nullptr, w0, 1, 0.0, 1.0, 0.5 * dt, s)) != DG_OK) return rc;
-        if ((rc = stage_general(ctx, w0, q, w1, 1.0, 0.0, 0.5 * dt, nullptr, 0.0, nullptr, 0.0,
-                                s)) != DG_OK)
-          return rc;
-        if ((rc = stage_general(ctx, w1, q, w2, 1.0, 0.0, dt, nullptr, 0.0, nullptr, 0.0, s)) !=
+        if ((rc = stage_general(ctx, w0, q, w1, 0.0, 0.5 * dt, nullptr, 0.0, nullptr, 0.0, s)) !=
             DG_OK)
           return rc;
-        if ((rc = stage_general(ctx, w2, q, q, -1.0 / 3.0, 1.0 / 3.0, dt / 6.0, w0, 1.0 / 3.0, w1,
-                                2.0 / 3.0, s)) != DG_OK)
+        if ((rc = stage_general(ctx, w1, q, w2, 0.0, dt, nullptr, 0.0, nullptr, 0.0, s)) != DG_OK)
+          return rc;
+        if ((rc = stage_general(ctx, w2, q, q, 1.0 / 3.0, dt / 6.0, w0, 1.0 / 3.0, w1, 2.0 / 3.0,
+                                s)) != DG_OK)
           return rc;
         break;
       }

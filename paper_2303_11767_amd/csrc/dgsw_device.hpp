@@ -21,8 +21,7 @@ struct GlobTab {
   T cF;          // 2 / dlambda: longitude volume and edge terms after M^-1
   T cG;          // 2 / dtheta:  latitude volume and edge terms after M^-1
   T g;           // gravity
-  T invR;        // 1 / radius
-  T two_omega;   // 2 Omega
+  T invR;        // 1 / radius (1 on the plane)
   T href;        // reference depth H (0: off)
   T two_href;    // 2 H: the (h, mode 00) coefficient of the constant H
   T alpha;       // fixed Rusanov speed when alpha_global
@@ -31,9 +30,10 @@ struct GlobTab {
 // Tables of one latitude row (the mass matrix depends on latitude only).
 template <typename T, int NP>
 struct RowTab {
-  T cosn[NP];     // cos(theta) at the row's latitude nodes
-  T sinn[NP];     // sin(theta)
-  T stil[NP];     // pressure-metric factor (balanced s~ or sin)
+  T cosn[NP];     // cos(theta) at the row's latitude nodes (1 on the plane)
+  T fc[NP];       // Coriolis part of the source factor: 2 Omega sin cos (f on the plane)
+  T snR[NP];      // sin(theta) / R: the metric part u sin / R (0 on the plane)
+  T stR[NP];      // pressure-metric factor (balanced s~ or sin) / R (0 on the plane)
   T BM[NP][NP];   // w_s sum_b' Minv[b][b'] P~_b'(eta_s), [s][b]
   T DM[NP][NP];   // w_s sum_b' Minv[b][b'] P~'_b'(eta_s), [s][b]
   T MN[NP];       // sum_b' Minv[b][b'] P~_b'(+1)
@@ -51,8 +51,9 @@ struct StageLaunch {
   const void *rows;     // RowTab<T, NP>[n_lat] on the device
   int n_lon, n_lat, E;
   int alpha_global;
+  int periodic_y = 0;   // 1: rows wrap (plane); 0: pole rows (sphere)
   int combine;          // 0: out = L(q); 1: out = c0 q0 + c1 (q + dt L(q));
-                        // 2: out = c0 q0 + c1 q + dt L(q) + ca qa + cb qb
+                        // 2: out = q0 + c1 (q - q0) + ca (qa - q0) + cb (qb - q0) + dt L(q)
   double c0, c1, dt;
   const void *qa = nullptr, *qb = nullptr;   // extra operands of combine == 2
   double ca = 0.0, cb = 0.0;

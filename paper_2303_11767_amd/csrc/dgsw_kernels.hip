@@ -1,5 +1,7 @@
 // HIP kernels of the modal DG shallow-water right-hand side on the sphere,
-// for gfx950 (64-wide wavefronts).
+// for gfx950 (64-wide wavefronts).  The same kernels run the doubly periodic
+// plane of section 4.2 (cos = 1, radius 1, constant f, rows that wrap), which
+// differs from the sphere only in its tables and the row wrap.
 //
 // One fused kernel per Runge-Kutta stage.  Work unit: one element, handled by
 // NP = r+1 lanes ("line lanes"); a 64-lane wavefront holds 64/NP elements and
@@ -15,7 +17,7 @@
 //             lane t = edge node s: the east/west traces
 //   halo      traces of the four neighbours at the shared edges, each from one
 //             row or column of the neighbour's coefficients (periodic in
-//             longitude, none across a pole)
+//             longitude, none across a pole; periodic in y on the plane)
 //   edges     Rusanov flux (eq. "rusanov") at edge node t of all four edges
 //   volume    fluxes F, G and sources S at the n nodes of column t, contracted
 //             over the latitude nodes with the inverse mass matrix folded in
@@ -26,7 +28,10 @@
 //             terms, giving row b of dq/dt = M^-1 h(q) (eq. "ode")
 //   epilogue  optional forcing, then either dq/dt, the Shu-Osher stage
 //             combination c0 q^n + c1 (q + dt dq/dt), or the general one
-//             c0 q^n + c1 q + dt dq/dt + ca qa + cb qb (classical RK4), stored
+//             q^n + c1 (q - q^n) + ca (qa - q^n) + cb (qb - q^n) + dt dq/dt
+//             (classical RK4); both written so that the weights of the states
+//             sum to one exactly in the working precision (no systematic
+//             mass drift from rounded coefficients such as 1/3), stored
 //             as row b.
 //
 // The weak form is that of eq. "dg_parts": volume term of F . grad(phi) plus
@@ -184,15 +189,21 @@ struct StageArgs {
   const T *qa, *qb;      // extra states of the general combination (may be null)
   const GlobTab<T, NP> *gt;
   const RowTab<T, NP> *rows;
-  int n_lon, n_lat, alpha_global, combine;
+  int n_lon, n_lat, alpha_global, combine, periodic_y;
   T c0, c1, dt, ca, cb;
+  T ce;                  // c0 + c1 - 1, formed in FP64 on the host (0 for the schemes here)
 };
 
 // One wavefront's share of a stage: GPW elements of one latitude row
 // (segment `seg` of row j), so the row's tables are wave-uniform (scalar
 // loads) and the pole tests are uniform branches.  tab and sh are this
 // wavefront's LDS slices (TB and (GPW+1)*SH values).
-template <typename T, int NP>
+// CM: the stage combination as a compile-time mode (0: dq/dt, 1: Shu-Osher,
+// 2: general) so each launch carries only its own epilogue, or CM_RUNTIME to
+// take 0 or 1 from A.combine (the ensemble kernels).
+constexpr int CM_RUNTIME = 3;
+
+template <typename T, int NP, int CM>
 __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int j, const int seg,
                                            const int lane, T *tab, T *sh) {
   using S_ = Shape<T, NP>;
@@ -203,7 +214,8 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
   const T *__restrict__ forcing = A.forcing;
   const GlobTab<T, NP> *__restrict__ gt = A.gt;
   const RowTab<T, NP> *__restrict__ rows = A.rows;
-  const int n_lon = A.n_lon, n_lat = A.n_lat, combine = A.combine;
+  const int n_lon = A.n_lon, n_lat = A.n_lat;
+  const int combine = CM == CM_RUNTIME ? (A.combine != 0 ? 1 : 0) : CM;
   const T c0 = A.c0, c1 = A.c1, dt = A.dt;
   int g = lane / NP, t = lane - g * NP;
   const bool idle = g >= GPW;          // the 64 mod NP spare lanes: a dummy LDS slot
@@ -214,7 +226,11 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
   const int e = j * n_lon + i;
   T *S = sh + g * SH;
   const RowTab<T, NP> *rt = rows + j;
-  const bool hasN = j < n_lat - 1, hasS = j > 0;
+  const bool periodic = A.periodic_y != 0;
+  const bool hasN = periodic || j < n_lat - 1, hasS = periodic || j > 0;
+  // north / south neighbours (rows wrap on the plane)
+  const int eN = j < n_lat - 1 ? e + n_lon : i;
+  const int eS = j > 0 ? e - n_lon : (n_lat - 1) * n_lon + i;
   const T H = gt->href, H2 = gt->two_href, grav = gt->g, invR = gt->invR;
   const bool fixed = A.alpha_global != 0;
   const T alpha = gt->alpha;
@@ -232,7 +248,7 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
     load_row<T, NP>(q + (size_t)eW * 3 * N + row_off + v * N, xW[v]);
   }
   if (hasN) {
-    const T *c = q + (size_t)(e + n_lon) * 3 * N + t;                    // column a = t
+    const T *c = q + (size_t)eN * 3 * N + t;                             // column a = t
 #pragma unroll
     for (int v = 0; v < 3; ++v)
 #pragma unroll
@@ -244,7 +260,7 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
       for (int k = 0; k < NP; ++k) xN[v][k] = T(0);
   }
   if (hasS) {
-    const T *c = q + (size_t)(e - n_lon) * 3 * N + t;
+    const T *c = q + (size_t)eS * 3 * N + t;
 #pragma unroll
     for (int v = 0; v < 3; ++v)
 #pragma unroll
@@ -343,7 +359,7 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
   if (hasS) {
     rusanov_theta<T>(nbS, trS, H, grav, fixed, alpha, GhS);
   }
-  const T fN = hasN ? rt->ctop * invR : T(0);   // zero flux through a pole
+  const T fN = hasN ? rt->ctop * invR : T(0);   // zero flux through a pole (sphere)
   const T fS = hasS ? rt->cbot * invR : T(0);
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
@@ -363,7 +379,6 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
   for (int v = 0; v < 2; ++v)
 #pragma unroll
     for (int b = 0; b < NP; ++b) ZS[v][b] = T(0);
-  const T two_omega = gt->two_omega;
 #pragma unroll
   for (int s = 0; s < NP; ++s) {
     const T dh = nd[0][s], hu = nd[1][s], hv = nd[2][s];
@@ -371,12 +386,12 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
     const T rh = dg_rcp(h);
     const T u = hu * rh, vv = hv * rh;
     const T pr = T(0.5) * grav * dh * (h + H);
-    const T c = rt->cosn[s], sn = rt->sinn[s], st = rt->stil[s];
+    const T c = rt->cosn[s];
     const T F0 = hu * invR, F1 = (hu * u + pr) * invR, F2 = hu * vv * invR;
     const T cR = c * invR;
     const T G0 = hv * cR, G1 = hv * u * cR, G2 = (hv * vv + pr) * cR;
-    const T C = sn * (two_omega * c + u * invR);
-    const T S1 = C * hv, S2 = -pr * st * invR - C * hu;
+    const T C = rt->fc[s] + u * rt->snR[s];       // f cos + u sin / R (f on the plane)
+    const T S1 = C * hv, S2 = -pr * rt->stR[s] - C * hu;
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
       const T bm = rt->BM[s][b], dm = rt->DM[s][b];
@@ -404,7 +419,7 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
 
   // ---- the epilogue's operands, loaded late to keep registers free: q (again,
   // from cache), q^n and the forcing
-  const bool use_q0 = combine && c0 != T(0);
+  const bool use_q0 = combine == 2 || (combine == 1 && c0 != T(0));
   T q0r[3][NP], fr[3][NP];
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
@@ -453,16 +468,22 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
       for (int p = 0; p < NP; ++p) acc += gt->D[p][a] * zd[p] + gt->B[p][a] * zb[p];
       acc -= cF * (gt->Pp[a] * XE - gt->Pm[a] * XW);
       acc += fr[v][a];
-      if (combine == 2)
-        res[a] = c0 * q0r[v][a] + c1 * qr[v][a] + dt * acc + A.ca * xa[a] + A.cb * xb[a];
-      else
-        res[a] = combine ? c0 * q0r[v][a] + c1 * (qr[v][a] + dt * acc) : acc;
+      if (combine == 2) {
+        const T b0 = q0r[v][a];
+        res[a] = b0 + dt * acc + (c1 * (qr[v][a] - b0) + (A.ca * (xa[a] - b0) + A.cb * (xb[a] - b0)));
+      } else if (combine) {
+        // c0 q0 + c1 y = y + c0 (q0 - y) + (c0 + c1 - 1) y, y = q + dt L
+        const T y = qr[v][a] + dt * acc;
+        res[a] = y + c0 * (q0r[v][a] - y) + A.ce * y;
+      } else {
+        res[a] = acc;
+      }
     }
     if (active) store_row<T, NP>(out + base + v * N, res);
   }
 }
 
-template <typename T, int NP, int WPB>
+template <typename T, int NP, int WPB, int CM>
 __global__ __launch_bounds__(64 * WPB) void k_dg_stage(StageArgs<T, NP> A, int segs) {
   using S_ = Shape<T, NP>;
   // WPB independent wavefronts per workgroup (fewer workgroups to dispatch on
@@ -474,7 +495,7 @@ __global__ __launch_bounds__(64 * WPB) void k_dg_stage(StageArgs<T, NP> A, int s
   const int blk = xcd_block(blockIdx.x, gridDim.x) * WPB + wv;
   if (blk >= segs * A.n_lat) return;      // spare wavefront of the last workgroup
   const int j = blk / segs;
-  stage_wave<T, NP>(A, j, blk - j * segs, threadIdx.x & 63, tab_all[wv], sh_all[wv]);
+  stage_wave<T, NP, CM>(A, j, blk - j * segs, threadIdx.x & 63, tab_all[wv], sh_all[wv]);
 }
 
 // expands to a switch over the runtime (dtype, np) that returns FN<T, NP>(args)
@@ -503,7 +524,7 @@ constexpr int lds_max_sh(int npmax) { return npmax == 0 ? 0 : (lds_sh(npmax) > l
 
 template <typename T, int NP>
 __device__ __forceinline__ void ens_case(const EnsItem &m, const T *q, const T *q0, T *out,
-                                         int combine, T c0, T c1, int lane, T *tab, T *sh) {
+                                         int combine, T c0, T ce, int lane, T *tab, T *sh) {
   StageArgs<T, NP> A;
   A.q = q + m.off;
   A.q0 = q0 ? q0 + m.off : nullptr;
@@ -516,11 +537,13 @@ __device__ __forceinline__ void ens_case(const EnsItem &m, const T *q, const T *
   A.n_lon = m.n_lon;
   A.n_lat = m.n_lat;
   A.alpha_global = m.alpha_global;
+  A.periodic_y = 0;
   A.combine = combine;
   A.c0 = c0;
-  A.c1 = c1;
+  A.c1 = T(0);
+  A.ce = ce;
   A.dt = T(m.dt);
-  stage_wave<T, NP>(A, m.j, m.seg, lane, tab, sh);
+  stage_wave<T, NP, CM_RUNTIME>(A, m.j, m.seg, lane, tab, sh);
 }
 
 // One launch per Runge-Kutta stage for a whole ensemble of meshes of different
@@ -534,7 +557,7 @@ template <typename T, int NPMAX, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_ens_stage(const T *__restrict__ q, const T *q0, T *out,
                                                         const EnsItem *__restrict__ items,
                                                         const int *__restrict__ bounds, int combine,
-                                                        T c0, T c1) {
+                                                        T c0, T ce) {
   __shared__ T tab_all[WPB][lds_max_tab(NPMAX)];
   __shared__ T sh_all[WPB][lds_max_sh(NPMAX)];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -544,17 +567,17 @@ __global__ __launch_bounds__(64 * WPB) void k_ens_stage(const T *__restrict__ q,
   for (int it = bounds[part] + wv; it < end; it += WPB) {
     const EnsItem m = items[it];
     switch (m.np) {
-      case 1: ens_case<T, 1>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
-      case 2: ens_case<T, 2>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
-      case 3: ens_case<T, 3>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
-      case 4: ens_case<T, 4>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
-      case 5: ens_case<T, 5>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
+      case 1: ens_case<T, 1>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 2: ens_case<T, 2>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 3: ens_case<T, 3>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 4: ens_case<T, 4>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 5: ens_case<T, 5>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
       default:
         if constexpr (NPMAX > 5) {
           switch (m.np) {
-            case 6: ens_case<T, (NPMAX > 5 ? 6 : 1)>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
-            case 7: ens_case<T, (NPMAX > 6 ? 7 : 1)>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
-            case 8: ens_case<T, (NPMAX > 7 ? 8 : 1)>(m, q, q0, out, combine, c0, c1, lane, tab, sh); break;
+            case 6: ens_case<T, (NPMAX > 5 ? 6 : 1)>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+            case 7: ens_case<T, (NPMAX > 6 ? 7 : 1)>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+            case 8: ens_case<T, (NPMAX > 7 ? 8 : 1)>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
             default: break;
           }
         }
@@ -570,7 +593,7 @@ template <typename T, int NP, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_ens_stage_np(const T *__restrict__ q, const T *q0, T *out,
                                                            const EnsItem *__restrict__ items,
                                                            const int *__restrict__ bounds, int combine,
-                                                           T c0, T c1) {
+                                                           T c0, T ce) {
   __shared__ T tab_all[WPB][Shape<T, NP>::TB];
   __shared__ T sh_all[WPB][(Shape<T, NP>::GPW + 1) * Shape<T, NP>::SH];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -578,7 +601,7 @@ __global__ __launch_bounds__(64 * WPB) void k_ens_stage_np(const T *__restrict__
   const int end = bounds[part + 1];
   for (int it = bounds[part] + wv; it < end; it += WPB) {
     const EnsItem m = items[it];
-    ens_case<T, NP>(m, q, q0, out, combine, c0, c1, lane, tab_all[wv], sh_all[wv]);
+    ens_case<T, NP>(m, q, q0, out, combine, c0, ce, lane, tab_all[wv], sh_all[wv]);
   }
 }
 
@@ -588,14 +611,14 @@ __global__ __launch_bounds__(64 * WPB) void k_ens_stage_np(const T *__restrict__
 template <typename T, int NP, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_ens_stage_flat(const T *__restrict__ q, const T *q0, T *out,
                                                              const EnsItem *__restrict__ items,
-                                                             int begin, int end, int combine, T c0, T c1) {
+                                                             int begin, int end, int combine, T c0, T ce) {
   __shared__ T tab_all[WPB][Shape<T, NP>::TB];
   __shared__ T sh_all[WPB][(Shape<T, NP>::GPW + 1) * Shape<T, NP>::SH];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int it = begin + xcd_block(blockIdx.x, gridDim.x) * WPB + wv;
   if (it >= end) return;
   const EnsItem m = items[it];
-  ens_case<T, NP>(m, q, q0, out, combine, c0, c1, lane, tab_all[wv], sh_all[wv]);
+  ens_case<T, NP>(m, q, q0, out, combine, c0, ce, lane, tab_all[wv], sh_all[wv]);
 }
 
 template <typename T, int NP, int WPB>
@@ -603,7 +626,7 @@ static hipError_t launch_ens_flat_t(const EnsLaunch &a, hipStream_t s) {
   const int n = a.end - a.begin;
   hipLaunchKernelGGL((k_ens_stage_flat<T, NP, WPB>), dim3((n + WPB - 1) / WPB), dim3(64 * WPB), 0, s,
                      static_cast<const T *>(a.q), static_cast<const T *>(a.q0),
-                     static_cast<T *>(a.out), a.items, a.begin, a.end, a.combine, T(a.c0), T(a.c1));
+                     static_cast<T *>(a.out), a.items, a.begin, a.end, a.combine, T(a.c0), T(a.c0 + a.c1 - 1.0));
   return hipGetLastError();
 }
 
@@ -611,7 +634,7 @@ template <typename T, int NP, int WPB>
 static hipError_t launch_ens_np_t(const EnsLaunch &a, hipStream_t s) {
   hipLaunchKernelGGL((k_ens_stage_np<T, NP, WPB>), dim3(a.parts), dim3(64 * WPB), 0, s,
                      static_cast<const T *>(a.q), static_cast<const T *>(a.q0),
-                     static_cast<T *>(a.out), a.items, a.bounds, a.combine, T(a.c0), T(a.c1));
+                     static_cast<T *>(a.out), a.items, a.bounds, a.combine, T(a.c0), T(a.c0 + a.c1 - 1.0));
   return hipGetLastError();
 }
 
@@ -642,7 +665,7 @@ template <typename T, int NPMAX, int WPB>
 static hipError_t launch_ens_t(const EnsLaunch &a, hipStream_t s) {
   hipLaunchKernelGGL((k_ens_stage<T, NPMAX, WPB>), dim3(a.parts), dim3(64 * WPB), 0, s,
                      static_cast<const T *>(a.q), static_cast<const T *>(a.q0),
-                     static_cast<T *>(a.out), a.items, a.bounds, a.combine, T(a.c0), T(a.c1));
+                     static_cast<T *>(a.out), a.items, a.bounds, a.combine, T(a.c0), T(a.c0 + a.c1 - 1.0));
   return hipGetLastError();
 }
 
@@ -734,9 +757,11 @@ static StageArgs<T, NP> stage_args(const StageLaunch &a) {
   A.n_lon = a.n_lon;
   A.n_lat = a.n_lat;
   A.alpha_global = a.alpha_global;
+  A.periodic_y = a.periodic_y;
   A.combine = a.combine;
   A.c0 = T(a.c0);
   A.c1 = T(a.c1);
+  A.ce = T(a.c0 + a.c1 - 1.0);
   A.dt = T(a.dt);
   return A;
 }
@@ -747,10 +772,24 @@ static hipError_t launch_stage_t(const StageLaunch &a, hipStream_t s) {
   const int segs = (a.n_lon + GPW - 1) / GPW;
   const int waves = segs * a.n_lat;
   const StageArgs<T, NP> A = stage_args<T, NP>(a);
-  if (waves >= 4096)
-    hipLaunchKernelGGL((k_dg_stage<T, NP, 4>), dim3((waves + 3) / 4), dim3(256), 0, s, A, segs);
-  else
-    hipLaunchKernelGGL((k_dg_stage<T, NP, 1>), dim3(waves), dim3(64), 0, s, A, segs);
+  const bool big = waves >= 4096;
+  const dim3 grid(big ? (waves + 3) / 4 : waves), block(big ? 256 : 64);
+  switch (a.combine) {
+    case 0:
+      if (big) hipLaunchKernelGGL((k_dg_stage<T, NP, 4, 0>), grid, block, 0, s, A, segs);
+      else hipLaunchKernelGGL((k_dg_stage<T, NP, 1, 0>), grid, block, 0, s, A, segs);
+      break;
+    case 1:
+      if (big) hipLaunchKernelGGL((k_dg_stage<T, NP, 4, 1>), grid, block, 0, s, A, segs);
+      else hipLaunchKernelGGL((k_dg_stage<T, NP, 1, 1>), grid, block, 0, s, A, segs);
+      break;
+    case 2:
+      if (big) hipLaunchKernelGGL((k_dg_stage<T, NP, 4, 2>), grid, block, 0, s, A, segs);
+      else hipLaunchKernelGGL((k_dg_stage<T, NP, 1, 2>), grid, block, 0, s, A, segs);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -789,7 +828,7 @@ static void fill_glob_t(const HostTables &t, double g, double radius, double ome
   G.cG = T(2.0 / t.dth);
   G.g = T(g);
   G.invR = T(1.0 / radius);
-  G.two_omega = T(2.0 * omega);
+  (void)omega;   // enters through the per-row source factors
   G.href = T(href);
   G.two_href = T(2.0 * href);
   G.alpha = T(alpha);
@@ -804,8 +843,9 @@ static void fill_rows_t(const HostTables &t, void *dst) {
     std::memset(&r, 0, sizeof(r));
     for (int s = 0; s < NP; ++s) {
       r.cosn[s] = T(t.cosn[j * NP + s]);
-      r.sinn[s] = T(t.sinn[j * NP + s]);
-      r.stil[s] = T(t.stil[j * NP + s]);
+      r.fc[s] = T(t.fc[j * NP + s]);
+      r.snR[s] = T(t.snR[j * NP + s]);
+      r.stR[s] = T(t.stR[j * NP + s]);
       for (int b = 0; b < NP; ++b) {
         r.BM[s][b] = T(t.BM[(j * NP + s) * NP + b]);
         r.DM[s][b] = T(t.DM[(j * NP + s) * NP + b]);

@@ -313,6 +313,7 @@ int learned_stage(dg_ctx *ctx, const dg_learned *net, const LearnWs &t, const vo
 int check_learned(const dg_ctx *ctx, const dg_learned *net, const void *workspace) {
   if (!ctx || !net || !workspace) return fail(DG_EINVAL, "NULL argument");
   if (ctx->np != 2) return fail(DG_EUNSUPPORTED, "the learned correction is defined for order 1");
+  if (ctx->periodic_y) return fail(DG_EUNSUPPORTED, "the learned correction is defined on the sphere");
   if (!net->params || !net->feat_mean || !net->feat_istd || !net->out_mean || !net->out_std)
     return fail(DG_EINVAL, "dg_learned has a NULL table");
   if (!(net->kappa >= 0.0)) return fail(DG_EINVAL, "kappa must be >= 0");

@@ -423,11 +423,13 @@ __global__ __launch_bounds__(256) void k_mass_delta(const double *__restrict__ p
   if (threadIdx.x == 0) *delta = (float)(-sh[0] / area);
 }
 
-// out = combine ? c0 q0 + c1 (q + dt (L1 + c)) : L1 + c, with c_(h,00) = delta.
+// out = combine ? c0 q0 + c1 (q + dt (L1 + c)) : L1 + c, with c_(h,00) = delta;
+// the combination is evaluated as y + c0 (q0 - y) + ce y, y = q + dt (L1 + c),
+// ce = c0 + c1 - 1 formed in FP64, so the weights sum to one exactly.
 template <typename T>
 __global__ __launch_bounds__(256) void k_learned_out(const T *__restrict__ q, const T *q0, const T *__restrict__ L1,
                                                      const float *__restrict__ C, const float *__restrict__ delta,
-                                                     int E, int combine, T c0, T c1, T dt, T *out) {
+                                                     int E, int combine, T c0, T ce, T dt, T *out) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= E * 12) return;
   const int k = idx % 12;
@@ -435,7 +437,8 @@ __global__ __launch_bounds__(256) void k_learned_out(const T *__restrict__ q, co
   const T l = L1[idx] + corr;
   if (combine) {
     const T qn = c0 != T(0) ? q0[idx] : T(0);
-    out[idx] = c0 * qn + c1 * (q[idx] + dt * l);
+    const T y = q[idx] + dt * l;
+    out[idx] = y + c0 * (qn - y) + ce * y;
   } else {
     out[idx] = l;
   }
@@ -460,11 +463,12 @@ hipError_t launch_correction(int dtype, const LearnedLaunch &a, hipStream_t s) {
   if (dtype == 0)
     hipLaunchKernelGGL(k_learned_out<double>, dim3(ob), dim3(256), 0, s, static_cast<const double *>(a.q),
                        static_cast<const double *>(a.q0), static_cast<const double *>(a.L1), a.C, a.delta, a.E,
-                       a.combine, a.c0, a.c1, a.dt, static_cast<double *>(a.out));
+                       a.combine, a.c0, a.c0 + a.c1 - 1.0, a.dt, static_cast<double *>(a.out));
   else
     hipLaunchKernelGGL(k_learned_out<float>, dim3(ob), dim3(256), 0, s, static_cast<const float *>(a.q),
                        static_cast<const float *>(a.q0), static_cast<const float *>(a.L1), a.C, a.delta, a.E,
-                       a.combine, (float)a.c0, (float)a.c1, (float)a.dt, static_cast<float *>(a.out));
+                       a.combine, (float)a.c0, (float)(a.c0 + a.c1 - 1.0), (float)a.dt,
+                       static_cast<float *>(a.out));
   return hipGetLastError();
 }
 

@@ -85,15 +85,22 @@ static bool invert(int n, std::vector<double> &A) {
   return true;
 }
 
-bool build_tables(int n_lon, int n_lat, int order, int metric, double radius,
-                  HostTables &t, const char **msg) {
+namespace {
+
+// Everything that depends on the row geometry only through cos(theta) of the
+// nodes, the row edges and the mass-matrix weight function: the 1-D basis
+// tables, the latitude mass matrix, its inverse folded into the quadrature
+// tables, and the mass diagnostic weights.  plane: cos = 1 everywhere.
+bool build_common(int n_lon, int n_lat, int order, double dlam, double dth, bool plane,
+                  double radius, HostTables &t, const char **msg) {
   const int np = order + 1;
   t.n_lon = n_lon;
   t.n_lat = n_lat;
   t.order = order;
   t.np = np;
-  t.dlam = 2.0 * kPi / n_lon;
-  t.dth = kPi / n_lat;
+  t.dlam = dlam;
+  t.dth = dth;
+  t.periodic_y = plane;
 
   std::vector<double> x, w;
   gauss_legendre(np, x, w);
@@ -137,19 +144,19 @@ bool build_tables(int n_lon, int n_lat, int order, int metric, double radius,
 
   for (int j = 0; j < n_lat; ++j) {
     const double tb = -0.5 * kPi + j * t.dth;
-    const double cb = (j == 0) ? 0.0 : std::cos(tb);
-    const double ct = (j == n_lat - 1) ? 0.0 : std::cos(tb + t.dth);
+    const double cb = plane ? 1.0 : (j == 0) ? 0.0 : std::cos(tb);
+    const double ct = plane ? 1.0 : (j == n_lat - 1) ? 0.0 : std::cos(tb + t.dth);
     t.cbot[j] = cb;
     t.ctop[j] = ct;
     for (int s = 0; s < np; ++s) {
       double th = tb + 0.5 * (1.0 + x[s]) * t.dth;
-      t.cosn[j * np + s] = std::cos(th);
-      t.sinn[j * np + s] = std::sin(th);
+      t.cosn[j * np + s] = plane ? 1.0 : std::cos(th);
+      t.sinn[j * np + s] = plane ? 0.0 : std::sin(th);
     }
     // latitude mass matrix
     std::vector<double> M(np * np, 0.0);
     for (int q = 0; q < nq; ++q) {
-      double wc = wq[q] * std::cos(tb + 0.5 * (1.0 + xq[q]) * t.dth);
+      double wc = wq[q] * (plane ? 1.0 : std::cos(tb + 0.5 * (1.0 + xq[q]) * t.dth));
       for (int b = 0; b < np; ++b)
         for (int c = 0; c < np; ++c) M[b * np + c] += wc * Pq[q * np + b] * Pq[q * np + c];
     }
@@ -175,6 +182,23 @@ bool build_tables(int n_lon, int n_lat, int order, int metric, double radius,
       t.MN[j * np + b] = mn;
       t.MS[j * np + b] = ms;
     }
+  }
+  return true;
+}
+
+}  // namespace
+
+bool build_tables(int n_lon, int n_lat, int order, int metric, double radius, double omega,
+                  HostTables &t, const char **msg) {
+  if (!build_common(n_lon, n_lat, order, 2.0 * kPi / n_lon, kPi / n_lat, false, radius, t, msg))
+    return false;
+  const int np = order + 1;
+  const std::vector<double> &w = t.w;
+  t.fc.assign(n_lat * np, 0.0);
+  t.snR.assign(n_lat * np, 0.0);
+  t.stR.assign(n_lat * np, 0.0);
+  for (int j = 0; j < n_lat; ++j) {
+    const double cb = t.cbot[j], ct = t.ctop[j];
     // metric factor of the pressure source
     if (metric == 0) {
       // beta_b = sum_s w_s cos(theta_s) P~'_b(eta_s) - (c_t P~_b(1) - c_b P~_b(-1));
@@ -193,7 +217,24 @@ bool build_tables(int n_lon, int n_lat, int order, int metric, double radius,
     } else {
       for (int s = 0; s < np; ++s) t.stil[j * np + s] = t.sinn[j * np + s];
     }
+    for (int s = 0; s < np; ++s) {
+      const int k = j * np + s;
+      t.fc[k] = 2.0 * omega * t.sinn[k] * t.cosn[k];
+      t.snR[k] = t.sinn[k] / radius;
+      t.stR[k] = t.stil[k] / radius;
+    }
   }
+  return true;
+}
+
+bool build_tables_plane(int nx, int ny, int order, double lx, double ly, double f,
+                        HostTables &t, const char **msg) {
+  if (!build_common(nx, ny, order, lx / nx, ly / ny, true, 1.0, t, msg)) return false;
+  const size_t n = (size_t)ny * (order + 1);
+  t.stil.assign(n, 0.0);
+  t.fc.assign(n, f);
+  t.snR.assign(n, 0.0);
+  t.stR.assign(n, 0.0);
   return true;
 }
 

@@ -29,6 +29,11 @@ struct HostTables {
   std::vector<double> B, D, Pp, Pm, w;
   // per latitude row j, node s: cos, sin, balanced or pointwise metric factor
   std::vector<double> cosn, sinn, stil;           // [j][s]
+  // source factors per row node: S_hu = (fc + u snR) hv,
+  // S_hv = -p stR - (fc + u snR) hu with p the pressure g h^2/2.  Sphere:
+  // fc = 2 Omega sin cos, snR = sin / R, stR = (s~ or sin) / R; plane: fc = f.
+  std::vector<double> fc, snR, stR;               // [j][s]
+  bool periodic_y = false;                        // plane: rows wrap, no poles
   std::vector<double> ctop, cbot;                 // cos at the north/south edge of row j (0 at poles)
   // per row, the inverse latitude mass matrix folded with quadrature tables:
   //   BM[j][s][b] = w_s sum_b' Minv_j[b][b'] P~_b'(eta_s)
@@ -42,7 +47,14 @@ struct HostTables {
 };
 
 // metric: 0 balanced, 1 pointwise.  Returns false (with msg) on failure.
-bool build_tables(int n_lon, int n_lat, int order, int metric, double radius,
+bool build_tables(int n_lon, int n_lat, int order, int metric, double radius, double omega,
                   HostTables &t, const char **msg);
+
+// Doubly periodic plane [0, lx] x [0, ly] with nx x ny elements and constant
+// Coriolis parameter f (section 4.2, the planar shallow-water setting): the
+// same tables with dlam = dx, dth = dy, cos = 1, no metric source and an
+// identity latitude mass matrix (radius 1).
+bool build_tables_plane(int nx, int ny, int order, double lx, double ly, double f,
+                        HostTables &t, const char **msg);
 
 }  // namespace dgsw

@@ -68,9 +68,33 @@ def test_descriptor_validation(kw, code):
     assert len(lib.dg_last_error()) > 0
 
 
+def _plane(**kw):
+    d = _lib.PlaneDesc()
+    d.abi_version, d.nx, d.ny, d.order, d.dtype, d.alpha_mode = 1, 8, 6, 3, 0, 0
+    d.alpha, d.lx, d.ly, d.gravity, d.f, d.h_ref = 0.0, 1e7, 1e7, 9.81, 1e-4, 0.0
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("kw,code", [
+    ({"abi_version": 0}, -1), ({"nx": 0}, -1), ({"ny": -1}, -1), ({"order": 8}, -6),
+    ({"dtype": 3}, -2), ({"alpha_mode": 2}, -1), ({"lx": 0.0}, -1), ({"ly": float("inf")}, -1),
+    ({"gravity": 0.0}, -1), ({"f": float("nan")}, -1), ({"h_ref": -5.0}, -1),
+])
+def test_plane_descriptor_validation(kw, code):
+    lib = _lib.load()
+    ctx = ctypes.c_void_p(123)
+    rc = lib.dg_init_plane(ctypes.byref(_plane(**kw)), None, ctypes.byref(ctx))
+    assert rc == code
+    assert ctx.value is None
+    assert len(lib.dg_last_error()) > 0
+
+
 def test_null_arguments():
     lib = _lib.load()
     assert lib.dg_init_mesh(None, None, None) == -1
+    assert lib.dg_init_plane(None, None, None) == -1
     assert lib.dg_free(None) == 0
     n = ctypes.c_int64()
     assert lib.dg_state_size(None, ctypes.byref(n)) == -1

@@ -195,6 +195,24 @@ def test_rk3_c1_100_steps(dg):
     np.testing.assert_allclose(m1, m.mass(got), rtol=1e-13)
 
 
+@pytest.mark.parametrize("scheme", [3, 4])
+def test_f32_mass_has_no_drift(dg, scheme):
+    """FP32, 2000 steps at 32 x 16, r = 1: the stage combinations keep their
+    weights summing to one exactly, so the h-mass only moves by rounding
+    noise (rounded weights such as 1/3 and 2/3 would add a drift of about
+    3e-8 of the mass per step)."""
+    say("f32 mass drift", scheme)
+    q, info = band_limited_state(32, 16, 1, 6, 1)
+    mesh = make(dg, 32, 16, 1, "f32")
+    qd = to_dev(q, "f32")
+    dt = dg.cfl_time_step(mesh, info.cmax, 0.1)
+    m0 = mesh.mass(qd)[0]
+    mesh.rk_step(qd, mesh.empty_work(scheme), dt, scheme=scheme, nsteps=2000)
+    m1 = mesh.mass(qd)[0]
+    say("  relative drift", (m1 - m0) / m0)
+    assert abs(m1 - m0) <= 2e-6 * abs(m0)
+
+
 @pytest.mark.parametrize("scheme,name", [(1, "RK1"), (2, "RK2"), (4, "RK4")])
 def test_rk_schemes_match_printed_tableaux(dg, scheme, name):
     """One step of RK1, RK2 and the classical RK4 (the library's low-storage

@@ -1,0 +1,151 @@
+"""GPU parity of the doubly periodic f-plane (section 4.2) against the planar
+oracle: the right-hand side at every order on ragged meshes in both
+precisions, degenerate meshes that are their own neighbours, lake at rest,
+and the paper's geostrophic-adjustment run (50 x 50 elements, r = 3, RK4,
+dt = 100 s) stepped against the oracle and conserving mass and the Coriolis
+momentum budget."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from dg_inputs import gaussian_bump_plane, random_plane_state
+from oracle import PlaneDG, butcher_step
+from parity_util import TOL, errors
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+G, F = 9.81, 1.0e-4
+LX, LY = 1.0e7, 0.8e7
+
+
+@pytest.fixture(scope="module")
+def dg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_11767_amd as dg
+    return dg
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(q, dtype):
+    return torch.from_numpy(np.ascontiguousarray(q)).to(
+        device="cuda", dtype=torch.float64 if dtype == "f64" else torch.float32).contiguous()
+
+
+def oracle_input(q, dtype):
+    return q.astype(np.float32).astype(np.float64) if dtype == "f32" else q
+
+
+def plane(dg, nx, ny, order, dtype, lx=LX, ly=LY, **kw):
+    href = kw.pop("h_ref", 1000.0 if dtype == "f32" else 0.0)
+    return dg.Plane(nx, ny, order, lx, ly, dtype=dtype, f=F, gravity=G, h_ref=href, **kw)
+
+
+def check_rhs(dg, nx, ny, order, dtype, seed, **kw):
+    say("plane rhs", nx, ny, order, dtype, seed, kw)
+    q = random_plane_state(nx, ny, order, LX, LY, seed)
+    qin = oracle_input(q, dtype)
+    okw = {k: v for k, v in kw.items() if k in ("alpha_mode", "alpha")}
+    m = PlaneDG(nx, ny, order, LX, LY, gravity=G, f=F, **okw)
+    ref, sc = m.rhs(qin), m.rhs_scale(qin)
+    got = plane(dg, nx, ny, order, dtype, **kw).rhs(to_dev(q, dtype)).cpu().numpy()
+    comp, norm = errors(got, ref, sc)
+    say("  componentwise", comp, "normwise", norm)
+    assert np.all(np.isfinite(got))
+    assert np.all(comp <= TOL[dtype]), (comp, norm)
+
+
+@pytest.mark.parametrize("order", range(8))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_plane_rhs_every_order_ragged(dg, order, dtype):
+    """13 x 7 elements: ragged last wavefront of each row, wrap in x inside
+    a wavefront and wrap in y between the first and last rows."""
+    check_rhs(dg, 13, 7, order, dtype, seed=200 + order)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_plane_rhs_paper_mesh(dg, dtype):
+    """50 x 50, r = 3: the mesh of the geostrophic-adjustment runs."""
+    check_rhs(dg, 50, 50, 3, dtype, seed=210)
+
+
+def test_plane_rhs_global_alpha(dg):
+    check_rhs(dg, 11, 6, 2, "f64", seed=211, alpha_mode="global", alpha=110.0)
+
+
+def test_plane_rhs_degenerate(dg):
+    """One row (its own north and south neighbour), one column, one element."""
+    check_rhs(dg, 9, 1, 2, "f64", seed=212)
+    check_rhs(dg, 1, 6, 3, "f64", seed=213)
+    check_rhs(dg, 1, 1, 1, "f32", seed=214)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_plane_lake_at_rest(dg, dtype):
+    say("plane lake at rest", dtype)
+    mesh = plane(dg, 20, 15, 3, dtype)
+    q = np.zeros((mesh.E, 3, mesh.N))
+    q[:, 0, 0] = 2000.0
+    d = mesh.rhs(to_dev(q, dtype)).abs().max().item()
+    if dtype == "f32":
+        assert d == 0.0          # with h_ref = 1000 the pressure is exactly g (h-H)(h+H)/2 = 0
+    else:
+        assert d <= 1e-13 * G * 1000.0 ** 2 / 2 / (LY / 15) * 16
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_geostrophic_adjustment_run(dg, dtype):
+    """Section 4.2's run: Gaussian bump (h0 = 1000 m, h1 = 5 m, sigma = L/20)
+    on the 1e7 m square, f = 1e-4, 50 x 50 elements, r = 3, classical RK4 with
+    dt = 100 s.  The first 10 steps against the oracle's literal tableau
+    steps; then the whole 36000 s (360 steps) on the GPU: finite, h-mass
+    conserved, and the domain momentum following the exact budget
+    d/dt (int hu, int hv) = f (int hv, -int hu) (zero here, since the fluid
+    starts at rest and the budget keeps it there)."""
+    say("geostrophic adjustment", dtype)
+    L = 1.0e7
+    tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "butcher_tableaux.json")))["RK4"]
+    q = gaussian_bump_plane(50, 50, 3, L, L)
+    m = PlaneDG(50, 50, 3, L, L, gravity=G, f=F)
+    ref = oracle_input(q, dtype)
+    for _ in range(10):
+        ref = butcher_step(m.rhs, ref, 100.0, tab["A"], tab["b"])
+    mesh = plane(dg, 50, 50, 3, dtype, lx=L, ly=L)
+    qd = to_dev(q, dtype)
+    work = mesh.empty_work(dg.DG_RK4)
+    m0 = mesh.mass(qd)
+    mesh.rk_step(qd, work, 100.0, scheme=dg.DG_RK4, nsteps=10)
+    got = qd.cpu().numpy().astype(np.float64)
+    dh = np.abs(got[:, 0] - ref[:, 0]).max() / 5.0          # relative to the bump
+    dm = np.abs(got[:, 1:] - ref[:, 1:]).max() / np.abs(ref[:, 1:]).max()
+    say("  10 steps: h difference / h1", dh, "momentum difference", dm)
+    assert dh < (1e-10 if dtype == "f64" else 2e-3)
+    assert dm < (1e-9 if dtype == "f64" else 2e-3)
+    mesh.rk_step(qd, work, 100.0, scheme=dg.DG_RK4, nsteps=350)
+    m1 = mesh.mass(qd)
+    say("  after 36000 s: mass", m0, "->", m1)
+    assert np.all(np.isfinite(m1))
+    assert abs(m1[0] - m0[0]) <= (1e-13 if dtype == "f64" else 1e-6) * abs(m0[0])
+    mom_scale = abs(m0[0]) * 1.0                             # 1 m/s over the domain
+    assert abs(m1[1]) <= (1e-9 if dtype == "f64" else 1e-4) * mom_scale
+    assert abs(m1[2]) <= (1e-9 if dtype == "f64" else 1e-4) * mom_scale
+
+
+def test_plane_rejects_learned(dg):
+    from paper_2303_11767_amd import learned
+    mesh = plane(dg, 8, 8, 1, "f64")
+    P = learned.param_count()
+    z = torch.zeros(P, dtype=torch.float32, device="cuda")
+    f = torch.zeros(108, dtype=torch.float32, device="cuda")
+    o = torch.ones((8, 12), dtype=torch.float32, device="cuda")
+    with pytest.raises(dg.DGError) as ei:
+        learned.LearnedRHS(mesh, z, f, f, o, o, kappa=1.0).rhs(mesh.empty_state().zero_())
+    assert ei.value.code == -6
