@@ -126,6 +126,17 @@ typedef struct {
 } dg_plane_desc;
 int dg_init_plane(const dg_plane_desc *desc, void *hip_stream, dg_ctx **out);
 
+/* Stage-kernel layout of a context.  DG_KERNEL_LINE: r+1 lanes per element,
+ * each lane one modal row / node column.  DG_KERNEL_HALF: 2(r+1) lanes per
+ * element, each lane half of a row's outputs and two of the four edges (twice
+ * the wavefronts, about half the instructions each).  Both compute the same
+ * right-hand side up to rounding (the half layout sums the volume integral
+ * in two halves).  dg_init_mesh / dg_init_plane pick one by mesh size; this
+ * call overrides it (DG_EINVAL for another value). */
+enum { DG_KERNEL_LINE = 0, DG_KERNEL_HALF = 1 };
+int dg_set_kernel(dg_ctx *ctx, int32_t kernel);
+int dg_get_kernel(const dg_ctx *ctx, int32_t *kernel);
+
 /* Release a context and its device tables.  NULL is accepted.  The caller
  * must make sure no enqueued work still uses the context. */
 int dg_free(dg_ctx *ctx);

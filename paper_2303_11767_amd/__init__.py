@@ -105,6 +105,18 @@ class Mesh:
         self._owns = owns
         self._forcing = None
 
+    # -- stage-kernel layout
+    @property
+    def kernel(self):
+        """"line" (r+1 lanes per element) or "half" (2(r+1) lanes)."""
+        k = ctypes.c_int32()
+        check(self._lib.dg_get_kernel(self._ctx, ctypes.byref(k)))
+        return "half" if k.value == 1 else "line"
+
+    @kernel.setter
+    def kernel(self, name):
+        check(self._lib.dg_set_kernel(self._ctx, {"line": 0, "half": 1}[name]))
+
     # -- sizes
     def state_size(self):
         n = ctypes.c_int64()

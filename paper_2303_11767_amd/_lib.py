@@ -14,6 +14,7 @@ DG_F64, DG_F32 = 0, 1
 DG_METRIC_BALANCED, DG_METRIC_POINTWISE = 0, 1
 DG_ALPHA_LOCAL, DG_ALPHA_GLOBAL = 0, 1
 DG_SSP_RK1, DG_SSP_RK2, DG_SSP_RK3, DG_RK4 = 1, 2, 3, 4
+DG_KERNEL_LINE, DG_KERNEL_HALF = 0, 1
 DG_OK, DG_EINVAL, DG_EDTYPE, DG_ENOMEM, DG_EHIP, DG_ENONFINITE, DG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
 ERROR_NAMES = {
@@ -22,7 +23,7 @@ ERROR_NAMES = {
 }
 
 # every symbol include/dgsw.h declares
-EXPORTS = ("dg_init_mesh", "dg_init_plane", "dg_free", "dg_state_size", "dg_work_size", "dg_min_width", "dg_rhs",
+EXPORTS = ("dg_init_mesh", "dg_init_plane", "dg_set_kernel", "dg_get_kernel", "dg_free", "dg_state_size", "dg_work_size", "dg_min_width", "dg_rhs",
            "dg_rk_stage", "dg_rk_step", "dg_mass", "dg_set_forcing", "dg_last_error",
            "dg_ens_init", "dg_ens_free", "dg_ens_state_size", "dg_ens_offsets", "dg_ens_member",
            "dg_ens_set_dt", "dg_ens_rhs", "dg_ens_rk_stage", "dg_ens_rk_step", "dg_ens_set_schedule",
@@ -76,6 +77,8 @@ def load():
     vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
     lib.dg_init_mesh.argtypes = [ctypes.POINTER(MeshDesc), vp, ctypes.POINTER(vp)]
     lib.dg_init_plane.argtypes = [ctypes.POINTER(PlaneDesc), vp, ctypes.POINTER(vp)]
+    lib.dg_set_kernel.argtypes = [vp, i32]
+    lib.dg_get_kernel.argtypes = [vp, ctypes.POINTER(i32)]
     lib.dg_free.argtypes = [vp]
     lib.dg_state_size.argtypes = [vp, i64p]
     lib.dg_work_size.argtypes = [vp, i32, i64p]

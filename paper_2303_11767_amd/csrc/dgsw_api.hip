@@ -91,6 +91,16 @@ int make_ctx(const dg_mesh_desc *desc, const dgsw::HostTables &t, hipStream_t s,
   dg_ctx *c = new dg_ctx();
   c->d = *desc;
   c->periodic_y = t.periodic_y ? 1 : 0;
+  // kernel layout, chosen from MI355X stage timings of both layouts: the
+  // half-line layout where the line layout leaves the GPU latency-bound (at
+  // most 2048 wavefronts, about two per SIMD) and for FP64 at r >= 5, where
+  // the line layout's registers allow only one wavefront per SIMD; the line
+  // layout otherwise
+  {
+    const int waves_line = dgsw::waves_per_row(desc->order + 1, desc->n_lon) * desc->n_lat;
+    const bool half = (desc->dtype == DG_F64 && desc->order >= 5) || waves_line <= 2048;
+    c->kernel = half ? DG_KERNEL_HALF : DG_KERNEL_LINE;
+  }
   c->np = desc->order + 1;
   c->N = c->np * c->np;
   c->E = desc->n_lon * desc->n_lat;
@@ -204,6 +214,19 @@ int dg_init_plane(const dg_plane_desc *p, void *hip_stream, dg_ctx **out) {
   return make_ctx(&d, t, static_cast<hipStream_t>(hip_stream), out);
 }
 
+int dg_set_kernel(dg_ctx *ctx, int32_t kernel) {
+  if (!ctx) return fail(DG_EINVAL, "ctx is NULL");
+  if (kernel != DG_KERNEL_LINE && kernel != DG_KERNEL_HALF) return fail(DG_EINVAL, "unknown kernel");
+  ctx->kernel = kernel;
+  return DG_OK;
+}
+
+int dg_get_kernel(const dg_ctx *ctx, int32_t *kernel) {
+  if (!ctx || !kernel) return fail(DG_EINVAL, "NULL argument");
+  *kernel = ctx->kernel;
+  return DG_OK;
+}
+
 int dg_free(dg_ctx *ctx) {
   release(ctx);
   return DG_OK;
@@ -253,6 +276,7 @@ static int stage(dg_ctx *c, const void *q, const void *q0, void *out, int combin
   a.E = c->E;
   a.alpha_global = c->d.alpha_mode == DG_ALPHA_GLOBAL;
   a.periodic_y = c->periodic_y;
+  a.variant = c->kernel;
   a.combine = combine;
   a.c0 = c0;
   a.c1 = c1;
@@ -280,6 +304,7 @@ static int stage_general(dg_ctx *c, const void *q, const void *q0, void *out, do
   a.E = c->E;
   a.alpha_global = c->d.alpha_mode == DG_ALPHA_GLOBAL;
   a.periodic_y = c->periodic_y;
+  a.variant = c->kernel;
   a.combine = 2;
   a.c0 = 1.0 - c1 - ca - cb;
   a.c1 = c1;

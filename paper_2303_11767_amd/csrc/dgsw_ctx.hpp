@@ -23,6 +23,7 @@ struct dg_ctx {
   double *d_proj1 = nullptr;   // [n_lat][2][np]: cos-weighted projection onto order 1
   double mass_area = 0.0;      // sum over elements of mass_w[j][0]
   int periodic_y = 0;          // 1: the doubly periodic plane
+  int kernel = 0;              // DG_KERNEL_LINE or DG_KERNEL_HALF
 };
 
 namespace dgsw {

@@ -52,6 +52,7 @@ struct StageLaunch {
   int n_lon, n_lat, E;
   int alpha_global;
   int periodic_y = 0;   // 1: rows wrap (plane); 0: pole rows (sphere)
+  int variant = 0;      // 0: NP lanes per element; 1: 2 NP lanes (half lines)
   int combine;          // 0: out = L(q); 1: out = c0 q0 + c1 (q + dt L(q));
                         // 2: out = q0 + c1 (q - q0) + ca (qa - q0) + cb (qb - q0) + dt L(q)
   double c0, c1, dt;

@@ -43,6 +43,7 @@
 // (hence the constants 2/dlambda and 2/dtheta).
 #include "dgsw_device.hpp"
 
+#include <cstddef>
 #include <cstring>
 #include <type_traits>
 
@@ -483,6 +484,383 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
   }
 }
 
+// ------------------------------------------------------------------ half-line variant
+// Same stage with 2 NP lanes per element: lane (h, t), h = 0 or 1, owns line t
+// as above but only half of each line's outputs (indices h K0 .. h K0 + K0 - 1,
+// K0 = ceil(NP / 2)), and half of the edge work: h = 0 the east and north
+// edges, h = 1 the west and south edges (traces, neighbour loads and Rusanov
+// fluxes).  Twice the wavefronts with about half the instructions and
+// registers each: more latency hiding where one wavefront per SIMD is all
+// a mesh provides, and higher occupancy on large meshes.  The two halves'
+// partial volume sums are added in LDS (h = 0 writes, h = 1 accumulates).
+template <typename T, int NP>
+struct ShapeH2 {
+  static constexpr int N = NP * NP;
+  static constexpr int GPW = 64 / (2 * NP);            // elements per wavefront
+  static constexpr bool SPARE = GPW * 2 * NP < 64;      // lanes left over: a dummy slot
+  static constexpr int K0 = (NP + 1) / 2;
+  static constexpr int NB = 3 * (NP + 2) * NP;
+  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  static constexpr int SH = cmax(NB + 12 * NP, 6 * NP * NP + 6 * NP);
+  static constexpr int SLOTS = GPW + (SPARE ? 1 : 0);
+  // LDS copy of the tables: the GlobTab prefix (B, D, Pp, Pm, w) then the
+  // RowTab prefix (cosn, fc, snR, stR, BM, DM, MN, MS)
+  static constexpr int oB = 0, oD = N, oPp = 2 * N, oPm = 2 * N + NP, oW = 2 * N + 2 * NP;
+  static constexpr int G1 = 2 * N + 3 * NP;
+  static constexpr int oCos = G1, oFc = G1 + NP, oSnR = G1 + 2 * NP, oStR = G1 + 3 * NP;
+  static constexpr int oBM = G1 + 4 * NP, oDM = oBM + N, oMN = oDM + N, oMS = oMN + NP;
+  static constexpr int TB = oMS + NP;
+  static constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
+  static constexpr int ROWALIGN = gcd(16, NP * (int)sizeof(T));
+  // alignment of a half row starting at h K0 (even NP only; odd NP: element)
+  static constexpr int HALFALIGN = NP % 2 == 0 ? gcd(ROWALIGN, K0 * (int)sizeof(T)) : (int)sizeof(T);
+};
+
+// K0 values of a modal row starting at index h K0 (clamped to the row for the
+// odd-NP tail, whose value is then unused)
+template <typename T, int NP>
+__device__ __forceinline__ void load_half(const T *row, int h, T (&r)[ShapeH2<T, NP>::K0]) {
+  using S_ = ShapeH2<T, NP>;
+  if (NP % 2 == 0) {
+    const T *p = static_cast<const T *>(__builtin_assume_aligned(row + h * S_::K0, S_::HALFALIGN));
+#pragma unroll
+    for (int k = 0; k < S_::K0; ++k) r[k] = p[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < S_::K0; ++k) {
+      const int a = h * S_::K0 + k;
+      r[k] = row[a < NP ? a : NP - 1];
+    }
+  }
+}
+
+template <typename T, int NP>
+__device__ __forceinline__ void store_half(T *row, int h, const T (&r)[ShapeH2<T, NP>::K0]) {
+  using S_ = ShapeH2<T, NP>;
+  if (NP % 2 == 0) {
+    T *p = static_cast<T *>(__builtin_assume_aligned(row + h * S_::K0, S_::HALFALIGN));
+#pragma unroll
+    for (int k = 0; k < S_::K0; ++k) p[k] = r[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < S_::K0; ++k)
+      if (h * S_::K0 + k < NP) row[h * S_::K0 + k] = r[k];
+  }
+}
+
+template <typename T, int NP, int CM>
+__device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const int j, const int seg,
+                                              const int lane, T *tab, T *sh) {
+  using S_ = ShapeH2<T, NP>;
+  constexpr int N = S_::N, GPW = S_::GPW, SH = S_::SH, NB = S_::NB, K0 = S_::K0;
+  static_assert(sizeof(GlobTab<T, NP>) >= sizeof(T) * S_::G1, "GlobTab prefix");
+  using RT_ = RowTab<T, NP>;
+  static_assert(offsetof(RT_, MS) == sizeof(T) * (S_::oMS - S_::G1), "RowTab prefix");
+  const T *__restrict__ q = A.q;
+  const T *q0 = A.q0;
+  T *out = A.out;
+  const T *__restrict__ forcing = A.forcing;
+  const GlobTab<T, NP> *__restrict__ gt = A.gt;
+  const RowTab<T, NP> *__restrict__ rt = A.rows + j;
+  const int n_lon = A.n_lon, n_lat = A.n_lat;
+  const int combine = CM == CM_RUNTIME ? (A.combine != 0 ? 1 : 0) : CM;
+  const T c0 = A.c0, c1 = A.c1, dt = A.dt;
+  int g = lane / (2 * NP), r = lane - g * 2 * NP;
+  const bool idle = g >= GPW;
+  if (idle) { g = GPW; r = lane - GPW * 2 * NP; }
+  const int h = r >= NP ? 1 : 0;
+  const int t = r - h * NP;
+  const int i_raw = seg * GPW + g;
+  const bool active = !idle && i_raw < n_lon;
+  const int i = i_raw < n_lon ? i_raw : n_lon - 1;
+  const int e = j * n_lon + i;
+  T *S = sh + g * SH;
+  const bool periodic = A.periodic_y != 0;
+  const bool hasN = periodic || j < n_lat - 1, hasS = periodic || j > 0;
+  const bool hasY = h ? hasS : hasN;                 // this half's latitude edge
+  const int eE = (i + 1 == n_lon) ? e + 1 - n_lon : e + 1;
+  const int eW = (i == 0) ? e - 1 + n_lon : e - 1;
+  const int eN = j < n_lat - 1 ? e + n_lon : i;
+  const int eS = j > 0 ? e - n_lon : (n_lat - 1) * n_lon + i;
+  const int eX = h ? eW : eE, eY = h ? eS : eN;
+  const T H = gt->href, H2 = gt->two_href, grav = gt->g, invR = gt->invR;
+  const bool fixed = A.alpha_global != 0;
+  const T alpha = gt->alpha;
+
+  // ---- global loads: own row b = t, this half's longitude neighbour row and
+  // latitude neighbour column
+  const size_t row_off = (size_t)t * NP;
+  const size_t base = (size_t)e * 3 * N + row_off;
+  T qr[3][NP], xX[3][NP], xY[3][NP];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    load_row<T, NP>(q + base + v * N, qr[v]);
+    load_row<T, NP>(q + (size_t)eX * 3 * N + row_off + v * N, xX[v]);
+  }
+  if (hasY) {
+    const T *c = q + (size_t)eY * 3 * N + t;
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) xY[v][k] = c[v * N + k * NP];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) xY[v][k] = T(0);
+  }
+  {
+    const T *g0 = &gt->B[0][0], *r0 = &rt->cosn[0];
+    for (int k = lane; k < S_::TB; k += 64) tab[k] = k < S_::G1 ? g0[k] : r0[k - S_::G1];
+  }
+  // per-lane coefficients: rows h K0 + k of B (clamped), this half's own edge
+  // (h = 0: +1, h = 1: -1) and the facing edge of its neighbours
+  T BP[K0][NP], PE[NP], PF[NP];
+#pragma unroll
+  for (int k = 0; k < K0; ++k)
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      const int p1 = K0 + k < NP ? K0 + k : NP - 1;
+      BP[k][a] = h ? gt->B[p1][a] : gt->B[k][a];
+    }
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    PE[a] = h ? gt->Pm[a] : gt->Pp[a];
+    PF[a] = h ? gt->Pp[a] : gt->Pm[a];
+  }
+
+  // ---- xi pass: A[v][p][b=t] for this half's p, the own edge row, the
+  // neighbour partial sums
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    T qa[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) qa[a] = qr[v][a];
+    if (v == 0 && t == 0) qa[0] -= H2;
+#pragma unroll
+    for (int k = 0; k < K0; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) acc += qa[a] * BP[k][a];
+      const int p = h * K0 + k;
+      if (NP % 2 == 0 || p < NP) S[(v * (NP + 2) + p) * NP + t] = acc;
+    }
+    T ae = T(0);
+#pragma unroll
+    for (int a = 0; a < NP; ++a) ae += qa[a] * PE[a];
+    S[(v * (NP + 2) + NP + h) * NP + t] = ae;
+    T ux = T(0), uy = T(0);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      T yx = xX[v][k], yy = xY[v][k];
+      if (v == 0 && t == 0 && k == 0) { yx -= H2; yy -= H2; }
+      ux += yx * PF[k];
+      uy += yy * PF[k];
+    }
+    S[NB + (h * 3 + v) * NP + t] = ux;          // slot 0: east, 1: west
+    S[NB + ((2 + h) * 3 + v) * NP + t] = uy;    // slot 2: north, 3: south
+  }
+  wave_sync();
+
+  // ---- eta pass: nodal values of column p = t at this half's nodes s, own
+  // and neighbour traces of this half's two edges
+  T nd[3][K0], trX[3], trY[3], nbX[3], nbY[3];
+  T bt[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) bt[k] = tab[S_::oB + t * NP + k];          // P~_k(xi_t)
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    T col[NP];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) col[b] = S[(v * (NP + 2) + t) * NP + b];
+#pragma unroll
+    for (int k = 0; k < K0; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int b = 0; b < NP; ++b) acc += col[b] * BP[k][b];
+      nd[v][k] = acc;
+    }
+    T ay = T(0), ax = T(0), nx = T(0), ny = T(0);
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      ay += col[b] * PE[b];
+      ax += S[(v * (NP + 2) + NP + h) * NP + b] * bt[b];
+      nx += S[NB + (h * 3 + v) * NP + b] * bt[b];
+      ny += S[NB + ((2 + h) * 3 + v) * NP + b] * bt[b];
+    }
+    trX[v] = ax; trY[v] = ay; nbX[v] = nx; nbY[v] = hasY ? ny : ay;
+  }
+  wave_sync();
+
+  // ---- Rusanov fluxes at edge node t of this half's two edges (minus side =
+  // west / south: the own trace for h = 0, the neighbour's for h = 1)
+  T FhX[3], GhY[3];
+  {
+    T qm[3], qp[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) { qm[v] = h ? nbX[v] : trX[v]; qp[v] = h ? trX[v] : nbX[v]; }
+    rusanov_lambda<T>(qm, qp, H, grav, fixed, alpha, FhX);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) { qm[v] = h ? nbY[v] : trY[v]; qp[v] = h ? trY[v] : nbY[v]; }
+    rusanov_theta<T>(qm, qp, H, grav, fixed, alpha, GhY);
+  }
+  const T fY = (h ? rt->cbot : rt->ctop) * invR;     // 0 at a pole edge
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    FhX[v] *= invR;
+    GhY[v] = hasY ? GhY[v] * fY : T(0);
+  }
+
+  // ---- volume: fluxes and sources at nodes (t, s) of this half, partial
+  // contraction over s
+  T ZD[3][NP], ZG[3][NP], ZS[2][NP];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int b = 0; b < NP; ++b) { ZD[v][b] = T(0); ZG[v][b] = T(0); }
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int b = 0; b < NP; ++b) ZS[v][b] = T(0);
+#pragma unroll
+  for (int k = 0; k < K0; ++k) {
+    const int s_raw = h * K0 + k;
+    const int s = s_raw < NP ? s_raw : NP - 1;
+    const bool valid = NP % 2 == 0 || s_raw < NP;
+    const T dh = nd[0][k], hu = nd[1][k], hv = nd[2][k];
+    const T hh = dh + H;
+    const T rh = dg_rcp(hh);
+    const T u = hu * rh, vv = hv * rh;
+    const T pr = T(0.5) * grav * dh * (hh + H);
+    const T c = tab[S_::oCos + s];
+    const T F0 = hu * invR, F1 = (hu * u + pr) * invR, F2 = hu * vv * invR;
+    const T cR = c * invR;
+    const T G0 = hv * cR, G1 = hv * u * cR, G2 = (hv * vv + pr) * cR;
+    const T C = tab[S_::oFc + s] + u * tab[S_::oSnR + s];
+    const T S1 = C * hv, S2 = -pr * tab[S_::oStR + s] - C * hu;
+    const T m = valid ? T(1) : T(0);
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      const T bm = m * tab[S_::oBM + s * NP + b], dm = m * tab[S_::oDM + s * NP + b];
+      ZD[0][b] += F0 * bm; ZD[1][b] += F1 * bm; ZD[2][b] += F2 * bm;
+      ZG[0][b] += G0 * dm; ZG[1][b] += G1 * dm; ZG[2][b] += G2 * dm;
+      ZS[0][b] += S1 * bm; ZS[1][b] += S2 * bm;
+    }
+  }
+  const T wt = tab[S_::oW + t], cF = gt->cF, cG = gt->cG;
+  // this half's latitude surface term: - G^_N MN (h = 0), + G^_S MS (h = 1)
+  T PV[3][NP], PG[3][NP];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      const T my = tab[S_::oMN + h * NP + b];
+      const T zg = ZG[v][b] + (h ? GhY[v] : -GhY[v]) * my;
+      const T zs = v == 0 ? T(0) : ZS[v - 1][b];
+      PV[v][b] = cF * wt * ZD[v][b];
+      PG[v][b] = wt * (cG * zg + zs);
+    }
+  if (h == 0) {
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int b = 0; b < NP; ++b) {
+        S[((v * 2 + 0) * NP + t) * NP + b] = PV[v][b];
+        S[((v * 2 + 1) * NP + t) * NP + b] = PG[v][b];
+      }
+  }
+#pragma unroll
+  for (int v = 0; v < 3; ++v) S[6 * NP * NP + (v * 2 + h) * NP + t] = FhX[v];
+  wave_sync();
+  if (h == 1) {
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int b = 0; b < NP; ++b) {
+        S[((v * 2 + 0) * NP + t) * NP + b] += PV[v][b];
+        S[((v * 2 + 1) * NP + t) * NP + b] += PG[v][b];
+      }
+  }
+  wave_sync();
+
+  // ---- epilogue operands for this half's modes a = h K0 + k of row b = t
+  const bool use_q0 = combine == 2 || (combine == 1 && c0 != T(0));
+  T qh[3][K0], q0h[3][K0], fh[3][K0];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+#pragma unroll
+    for (int k = 0; k < K0; ++k) { qh[v][k] = T(0); q0h[v][k] = T(0); fh[v][k] = T(0); }
+    if (combine) load_half<T, NP>(q + base + v * N, h, qh[v]);
+    if (use_q0) load_half<T, NP>(q0 + base + v * N, h, q0h[v]);
+    if (forcing) load_half<T, NP>(forcing + base + v * N, h, fh[v]);
+  }
+
+  // ---- xi pass back to modes: lane t = latitude degree b, this half's a
+  T bmt[NP], DA[NP][K0], BA[NP][K0], PpA[K0], PmA[K0];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) bmt[p] = tab[S_::oBM + p * NP + t];       // BM[p][t]
+#pragma unroll
+  for (int k = 0; k < K0; ++k) {
+    const int a_raw = h * K0 + k;
+    const int a = a_raw < NP ? a_raw : NP - 1;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      DA[p][k] = tab[S_::oD + p * NP + a];
+      BA[p][k] = tab[S_::oB + p * NP + a];
+    }
+    PpA[k] = tab[S_::oPp + a];
+    PmA[k] = tab[S_::oPm + a];
+  }
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    T zd[NP], zb[NP];
+    T XE = T(0), XW = T(0);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      zd[p] = S[((v * 2 + 0) * NP + p) * NP + t];
+      zb[p] = S[((v * 2 + 1) * NP + p) * NP + t];
+      XE += S[6 * NP * NP + (v * 2 + 0) * NP + p] * bmt[p];
+      XW += S[6 * NP * NP + (v * 2 + 1) * NP + p] * bmt[p];
+    }
+    T xa[K0], xb[K0];
+#pragma unroll
+    for (int k = 0; k < K0; ++k) xa[k] = xb[k] = T(0);
+    if (combine == 2 && A.qa) load_half<T, NP>(A.qa + base + v * N, h, xa);
+    if (combine == 2 && A.qb) load_half<T, NP>(A.qb + base + v * N, h, xb);
+    T res[K0];
+#pragma unroll
+    for (int k = 0; k < K0; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) acc += DA[p][k] * zd[p] + BA[p][k] * zb[p];
+      acc -= cF * (PpA[k] * XE - PmA[k] * XW);
+      acc += fh[v][k];
+      if (combine == 2) {
+        const T b0 = q0h[v][k];
+        res[k] = b0 + dt * acc + (c1 * (qh[v][k] - b0) + (A.ca * (xa[k] - b0) + A.cb * (xb[k] - b0)));
+      } else if (combine) {
+        const T y = qh[v][k] + dt * acc;
+        res[k] = y + c0 * (q0h[v][k] - y) + A.ce * y;
+      } else {
+        res[k] = acc;
+      }
+    }
+    if (active) store_half<T, NP>(out + base + v * N, h, res);
+  }
+}
+
+template <typename T, int NP, int WPB, int CM>
+__global__ __launch_bounds__(64 * WPB) void k_dg_stage_h2(StageArgs<T, NP> A, int segs) {
+  using S_ = ShapeH2<T, NP>;
+  __shared__ T tab_all[WPB][S_::TB];
+  __shared__ T sh_all[WPB][S_::SLOTS * S_::SH];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int blk = xcd_block(blockIdx.x, gridDim.x) * WPB + wv;
+  if (blk >= segs * A.n_lat) return;
+  const int j = blk / segs;
+  stage_wave_h2<T, NP, CM>(A, j, blk - j * segs, threadIdx.x & 63, tab_all[wv], sh_all[wv]);
+}
+
 template <typename T, int NP, int WPB, int CM>
 __global__ __launch_bounds__(64 * WPB) void k_dg_stage(StageArgs<T, NP> A, int segs) {
   using S_ = Shape<T, NP>;
@@ -768,10 +1146,34 @@ static StageArgs<T, NP> stage_args(const StageLaunch &a) {
 
 template <typename T, int NP>
 static hipError_t launch_stage_t(const StageLaunch &a, hipStream_t s) {
+  const StageArgs<T, NP> A = stage_args<T, NP>(a);
+  if (a.variant == 1) {
+    constexpr int GPW = ShapeH2<T, NP>::GPW;
+    const int segs = (a.n_lon + GPW - 1) / GPW;
+    const int waves = segs * a.n_lat;
+    const bool big = waves >= 4096;
+    const dim3 grid(big ? (waves + 3) / 4 : waves), block(big ? 256 : 64);
+    switch (a.combine) {
+      case 0:
+        if (big) hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 4, 0>), grid, block, 0, s, A, segs);
+        else hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 1, 0>), grid, block, 0, s, A, segs);
+        break;
+      case 1:
+        if (big) hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 4, 1>), grid, block, 0, s, A, segs);
+        else hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 1, 1>), grid, block, 0, s, A, segs);
+        break;
+      case 2:
+        if (big) hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 4, 2>), grid, block, 0, s, A, segs);
+        else hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 1, 2>), grid, block, 0, s, A, segs);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   constexpr int GPW = Shape<T, NP>::GPW;
   const int segs = (a.n_lon + GPW - 1) / GPW;
   const int waves = segs * a.n_lat;
-  const StageArgs<T, NP> A = stage_args<T, NP>(a);
   const bool big = waves >= 4096;
   const dim3 grid(big ? (waves + 3) / 4 : waves), block(big ? 256 : 64);
   switch (a.combine) {

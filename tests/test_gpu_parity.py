@@ -47,14 +47,16 @@ def oracle_input(q, dtype):
     return q.astype(np.float32).astype(np.float64) if dtype == "f32" else q
 
 
-def check_rhs(dg, n_lon, n_lat, order, dtype, L, seed, **kw):
-    say("rhs", n_lon, n_lat, order, dtype, L, seed, kw)
+def check_rhs(dg, n_lon, n_lat, order, dtype, L, seed, kernel=None, **kw):
+    say("rhs", n_lon, n_lat, order, dtype, L, seed, kernel, kw)
     q, _ = band_limited_state(n_lon, n_lat, order, L, seed)
     qin = oracle_input(q, dtype)
     okw = {k: v for k, v in kw.items() if k in ("metric", "alpha_mode", "alpha")}
     m = SphereDG(n_lon, n_lat, order, **okw)
     ref, sc = m.rhs(qin), m.rhs_scale(qin)
     mesh = make(dg, n_lon, n_lat, order, dtype, **kw)
+    if kernel:
+        mesh.kernel = kernel
     got = mesh.rhs(to_dev(q, dtype)).cpu().numpy()
     comp, norm = errors(got, ref, sc)
     say("  componentwise", comp, "normwise", norm)
@@ -64,39 +66,48 @@ def check_rhs(dg, n_lon, n_lat, order, dtype, L, seed, **kw):
 
 
 # ---------------------------------------------------------------- right-hand side
+KERNELS = ["line", "half"]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("order", range(8))
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_rhs_every_order_ragged(dg, order, dtype):
+def test_rhs_every_order_ragged(dg, order, dtype, kernel):
     """13 x 7 elements: several wavefronts and a ragged last one, periodic
-    wrap inside a wavefront, both poles."""
-    check_rhs(dg, 13, 7, order, dtype, L=4, seed=100 + order)
+    wrap inside a wavefront, both poles; both kernel layouts."""
+    check_rhs(dg, 13, 7, order, dtype, L=4, seed=100 + order, kernel=kernel)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_rhs_c1(dg, dtype):
+def test_rhs_c1(dg, dtype, kernel):
     """r = 1, 32 x 16 (the FP64 workload of the smallest configuration)."""
-    check_rhs(dg, 32, 16, 1, dtype, L=6, seed=1)
+    check_rhs(dg, 32, 16, 1, dtype, L=6, seed=1, kernel=kernel)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_rhs_c2(dg, dtype):
+def test_rhs_c2(dg, dtype, kernel):
     """r = 3, 180 x 90, band-limited l <= 16: the benchmark workload."""
-    check_rhs(dg, 180, 90, 3, dtype, L=16, seed=2)
+    check_rhs(dg, 180, 90, 3, dtype, L=16, seed=2, kernel=kernel)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_rhs_c3(dg, dtype):
+def test_rhs_c3(dg, dtype, kernel):
     """r = 5, 360 x 180, l <= 32."""
-    check_rhs(dg, 360, 180, 5, dtype, L=32, seed=3)
+    check_rhs(dg, 360, 180, 5, dtype, L=32, seed=3, kernel=kernel)
 
 
-def test_rhs_degenerate_meshes(dg):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_rhs_degenerate_meshes(dg, kernel):
     """One row (both edges are poles), one column (the element is its own
     east and west neighbour), a single element."""
-    check_rhs(dg, 9, 1, 2, "f64", L=3, seed=7)
-    check_rhs(dg, 1, 6, 2, "f64", L=3, seed=8)
-    check_rhs(dg, 1, 1, 1, "f64", L=2, seed=9)
-    check_rhs(dg, 2, 2, 3, "f32", L=2, seed=10)
+    check_rhs(dg, 9, 1, 2, "f64", L=3, seed=7, kernel=kernel)
+    check_rhs(dg, 1, 6, 2, "f64", L=3, seed=8, kernel=kernel)
+    check_rhs(dg, 1, 1, 1, "f64", L=2, seed=9, kernel=kernel)
+    check_rhs(dg, 2, 2, 3, "f32", L=2, seed=10, kernel=kernel)
+    check_rhs(dg, 1, 1, 0, "f32", L=1, seed=11, kernel=kernel)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -106,20 +117,24 @@ def test_rhs_pointwise_and_global_alpha(dg, dtype):
     check_rhs(dg, 24, 12, 3, dtype, L=6, seed=12, alpha_mode="global", alpha=350.0)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("order", [1, 3, 5])
-def test_lake_at_rest(dg, order):
+def test_lake_at_rest(dg, order, kernel):
     n_lon, n_lat = 40, 20
-    say("lake", order)
+    say("lake", order, kernel)
     q = lake_at_rest_state(n_lon, n_lat, order, 1e4)
     m = SphereDG(n_lon, n_lat, order)
     sc = m.rhs_scale(q)
-    d64 = make(dg, n_lon, n_lat, order, "f64").rhs(to_dev(q, "f64")).cpu().numpy()
-    assert (np.abs(d64) / sc).max() <= TOL["f64"]
-    # FP32 with the reference depth equal to the lake depth: exactly zero
-    d32 = make(dg, n_lon, n_lat, order, "f32", h_ref=1e4).rhs(to_dev(q, "f32")).cpu().numpy()
-    assert np.abs(d32).max() == 0.0
-    d64h = make(dg, n_lon, n_lat, order, "f64", h_ref=1e4).rhs(to_dev(q, "f64")).cpu().numpy()
-    assert np.abs(d64h).max() == 0.0
+
+    def run(dtype, **kw):
+        mesh = make(dg, n_lon, n_lat, order, dtype, **kw)
+        mesh.kernel = kernel
+        return mesh.rhs(to_dev(q, dtype)).cpu().numpy()
+
+    assert (np.abs(run("f64")) / sc).max() <= TOL["f64"]
+    # with the reference depth equal to the lake depth: exactly zero
+    assert np.abs(run("f32", h_ref=1e4)).max() == 0.0
+    assert np.abs(run("f64", h_ref=1e4)).max() == 0.0
 
 
 def test_forcing_is_added(dg):
@@ -156,15 +171,17 @@ def test_determinism(dg):
 
 
 # ---------------------------------------------------------------- time stepping
-def test_ssp_rk3_one_step_parity(dg):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_ssp_rk3_one_step_parity(dg, kernel):
     """One SSP-RK3 step at 180 x 90, r = 3, FP64: every stage's error is
     componentwise within the bar, so the step agrees to dt times it."""
-    say("rk3 one step c2")
+    say("rk3 one step c2", kernel)
     q, info = band_limited_state(180, 90, 3, 16, 2)
     m = SphereDG(180, 90, 3)
     dt = m.cfl_time_step(info.cmax, 0.1)
     ref = m.ssp_rk3_step(q, dt)
     mesh = make(dg, 180, 90, 3, "f64")
+    mesh.kernel = kernel
     qd = to_dev(q, "f64")
     mesh.rk_step(qd, mesh.empty_work(), dt)
     got = qd.cpu().numpy()
@@ -328,15 +345,17 @@ def test_min_width_matches_oracle_time_step(dg):
         assert abs(dg.cfl_time_step(mesh, 333.0, 0.1) - m.cfl_time_step(333.0, 0.1)) <= 1e-13 * m.cfl_time_step(333.0, 0.1)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_c2_trajectory_rhs_parity(dg, dtype):
+def test_c2_trajectory_rhs_parity(dg, dtype, kernel):
     """180 x 90, r = 3: 1000 SSP-RK3 steps at CFL 0.1 on the GPU; every 100
     steps the GPU right-hand side of the current GPU state is compared with
     the oracle's on the same state; h-mass drift reported and bounded."""
-    say("c2 trajectory", dtype)
+    say("c2 trajectory", dtype, kernel)
     q, info = band_limited_state(180, 90, 3, 16, 2)
     m = SphereDG(180, 90, 3)
     mesh = make(dg, 180, 90, 3, dtype)
+    mesh.kernel = kernel
     qd = to_dev(q, dtype)
     work = mesh.empty_work()
     dt = dg.cfl_time_step(mesh, info.cmax, 0.1)

@@ -49,26 +49,29 @@ def plane(dg, nx, ny, order, dtype, lx=LX, ly=LY, **kw):
     return dg.Plane(nx, ny, order, lx, ly, dtype=dtype, f=F, gravity=G, h_ref=href, **kw)
 
 
-def check_rhs(dg, nx, ny, order, dtype, seed, **kw):
-    say("plane rhs", nx, ny, order, dtype, seed, kw)
+def check_rhs(dg, nx, ny, order, dtype, seed, kernel="line", **kw):
+    say("plane rhs", nx, ny, order, dtype, seed, kernel, kw)
     q = random_plane_state(nx, ny, order, LX, LY, seed)
     qin = oracle_input(q, dtype)
     okw = {k: v for k, v in kw.items() if k in ("alpha_mode", "alpha")}
     m = PlaneDG(nx, ny, order, LX, LY, gravity=G, f=F, **okw)
     ref, sc = m.rhs(qin), m.rhs_scale(qin)
-    got = plane(dg, nx, ny, order, dtype, **kw).rhs(to_dev(q, dtype)).cpu().numpy()
+    mesh = plane(dg, nx, ny, order, dtype, **kw)
+    mesh.kernel = kernel
+    got = mesh.rhs(to_dev(q, dtype)).cpu().numpy()
     comp, norm = errors(got, ref, sc)
     say("  componentwise", comp, "normwise", norm)
     assert np.all(np.isfinite(got))
     assert np.all(comp <= TOL[dtype]), (comp, norm)
 
 
+@pytest.mark.parametrize("kernel", ["line", "half"])
 @pytest.mark.parametrize("order", range(8))
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_plane_rhs_every_order_ragged(dg, order, dtype):
+def test_plane_rhs_every_order_ragged(dg, order, dtype, kernel):
     """13 x 7 elements: ragged last wavefront of each row, wrap in x inside
     a wavefront and wrap in y between the first and last rows."""
-    check_rhs(dg, 13, 7, order, dtype, seed=200 + order)
+    check_rhs(dg, 13, 7, order, dtype, seed=200 + order, kernel=kernel)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -81,11 +84,12 @@ def test_plane_rhs_global_alpha(dg):
     check_rhs(dg, 11, 6, 2, "f64", seed=211, alpha_mode="global", alpha=110.0)
 
 
-def test_plane_rhs_degenerate(dg):
+@pytest.mark.parametrize("kernel", ["line", "half"])
+def test_plane_rhs_degenerate(dg, kernel):
     """One row (its own north and south neighbour), one column, one element."""
-    check_rhs(dg, 9, 1, 2, "f64", seed=212)
-    check_rhs(dg, 1, 6, 3, "f64", seed=213)
-    check_rhs(dg, 1, 1, 1, "f32", seed=214)
+    check_rhs(dg, 9, 1, 2, "f64", seed=212, kernel=kernel)
+    check_rhs(dg, 1, 6, 3, "f64", seed=213, kernel=kernel)
+    check_rhs(dg, 1, 1, 1, "f32", seed=214, kernel=kernel)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
