@@ -121,7 +121,6 @@ TrainWs carve_train(void *ws, int64_t rows, size_t *bytes) {
 struct LearnWs {
   Weights w;
   void *L1;
-  __bf16 *Xb, *H1, *H2;
   float *Y, *C, *delta;
   double *partial;
 };
@@ -132,9 +131,6 @@ LearnWs carve_learn(void *ws, const dg_ctx *ctx, size_t *bytes) {
   const int64_t E = ctx->E;
   t.w = carve_weights(c, false);
   t.L1 = c.take<char>(E * 12 * ctx->elem_bytes);
-  t.Xb = c.take<__bf16>(E * kInPad);
-  t.H1 = c.take<__bf16>(E * kHidden);
-  t.H2 = c.take<__bf16>(E * kHidden);
   t.Y = c.take<float>(E * kOutPad);
   t.C = c.take<float>(E * 12);
   t.partial = c.take<double>((E + 255) / 256);
@@ -176,8 +172,8 @@ int dg_mlp_forward(const float *params, const float *X, int64_t rows, float *Y, 
   TrainWs t = carve_train(workspace, rows, nullptr);
   hipError_t e;
   if ((e = prep(params, t.w, s)) != hipSuccess) return hip_fail(e, "weight preparation");
-  if ((e = dgsw::launch_to_bf16(X, (int)rows, kFeatures, kInPad, t.Xb, s)) != hipSuccess) return hip_fail(e, "features");
-  if ((e = forward(params, t.w, t.Xb, (int)rows, nullptr, t.H1, nullptr, t.H2, t.Y, s)) != hipSuccess)
+  if ((e = dgsw::launch_mlp_fused(0, nullptr, 0, 0, nullptr, nullptr, X, (int)rows, t.w.W1t, t.w.W2t, t.w.W3t,
+                                  params + ob1, params + ob2, t.w.b3p, t.Y, s)) != hipSuccess)
     return hip_fail(e, "forward");
   if ((e = dgsw::launch_unpad(t.Y, (int)rows, kOut, kOutPad, Y, s)) != hipSuccess) return hip_fail(e, "output");
   return DG_OK;
@@ -296,10 +292,10 @@ int learned_stage(dg_ctx *ctx, const dg_learned *net, const LearnWs &t, const vo
   a.alpha_global = ctx->d.alpha_mode == DG_ALPHA_GLOBAL; a.combine = 0; a.c0 = 0.0; a.c1 = 1.0; a.dt = 0.0;
   hipError_t e = dgsw::launch_stage(dt_, ctx->np, a, s);
   if (e != hipSuccess) return hip_fail(e, "r = 1 stage launch");
-  if ((e = dgsw::launch_features(dt_, q, ctx->d.n_lon, ctx->d.n_lat, net->feat_mean, net->feat_istd, kInPad, t.Xb, s)) !=
-      hipSuccess)
-    return hip_fail(e, "features launch");
-  if ((e = forward(net->params, t.w, t.Xb, ctx->E, nullptr, t.H1, nullptr, t.H2, t.Y, s)) != hipSuccess)
+  // features and the whole network in one launch (hidden layers in LDS)
+  if ((e = dgsw::launch_mlp_fused(dt_, q, ctx->d.n_lon, ctx->d.n_lat, net->feat_mean, net->feat_istd, nullptr,
+                                  ctx->E, t.w.W1t, t.w.W2t, t.w.W3t, net->params + ob1, net->params + ob2, t.w.b3p,
+                                  t.Y, s)) != hipSuccess)
     return hip_fail(e, "network launch");
   dgsw::LearnedLaunch l;
   l.Y = t.Y; l.ldy = kOutPad; l.L1 = t.L1; l.omean = net->out_mean; l.ostd = net->out_std;

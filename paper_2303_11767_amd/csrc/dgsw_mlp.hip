@@ -127,6 +127,148 @@ hipError_t launch_gemm(bool a_kc, bool b_kc, int epi, const GemmArgs &g, hipStre
   return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------------------------ fused inference
+// The whole network on 64 rows per workgroup (4 wavefronts): the BF16 inputs
+// (stencil features computed from an r = 1 state, or given FP32 rows) and
+// both hidden layers stay in LDS; only the weights (from L2) and the FP32
+// outputs touch global memory.  Each product is computed transposed,
+// out^T = W in^T: the weights are the MFMA A operand (row = unit, 8
+// consecutive k per lane) and the LDS rows the B operand, so every lane ends
+// with 4 consecutive units of one row and writes them as one 8-byte LDS store.
+// Same rounding points as the unfused path: BF16 inputs, weights and hidden
+// activations, FP32 accumulation, bias and GELU in FP32.
+constexpr int kRows = 64;                 // rows per workgroup
+constexpr int kLd = kHidden + 8;          // LDS row stride in BF16 (+16 B: no bank conflicts)
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// One hidden layer for the 64 rows: wavefront wv computes units
+// [64 wv, 64 wv + 64) of out = gelu(in W^T + b), K inputs per row.
+template <int K>
+__device__ __forceinline__ void fused_hidden(const __bf16 *__restrict__ Wt, const float *__restrict__ bias,
+                                             const __bf16 *in, __bf16 *out, int wv, int lane) {
+  const int r = lane & 15, kq = (lane >> 4) * 8;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const __bf16 *wrow[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) wrow[nt] = Wt + (size_t)(64 * wv + 16 * nt + r) * K + kq;
+  bf16x8 a[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) a[nt] = *reinterpret_cast<const bf16x8 *>(wrow[nt]);
+#pragma unroll 2
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf16x8 an[4];
+    const int kn = k0 + 32 < K ? k0 + 32 : k0;          // prefetch of the next weights
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) an[nt] = *reinterpret_cast<const bf16x8 *>(wrow[nt] + kn);
+    bf16x8 b[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) b[mt] = *reinterpret_cast<const bf16x8 *>(in + (16 * mt + r) * kLd + k0 + kq);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+        acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[nt], b[mt], acc[nt][mt], 0, 0, 0);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) a[nt] = an[nt];
+  }
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int n0 = 64 * wv + 16 * nt + (lane >> 4) * 4;
+    const f32x4 bv = *reinterpret_cast<const f32x4 *>(bias + n0);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      bf16x4 h;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[i] = (__bf16)gelu_f(acc[nt][mt][i] + bv[i]);
+      *reinterpret_cast<bf16x4 *>(out + (16 * mt + r) * kLd + n0) = h;
+    }
+  }
+}
+
+// FROM_Q: features of the r = 1 state q (as k_features); else rows of X[rows][108].
+template <typename T, bool FROM_Q>
+__global__ __launch_bounds__(256) void k_mlp_fused(const T *__restrict__ q, int n_lon, int n_lat,
+                                                   const float *__restrict__ fmean, const float *__restrict__ fistd,
+                                                   const float *__restrict__ X, int rows,
+                                                   const __bf16 *__restrict__ W1t, const __bf16 *__restrict__ W2t,
+                                                   const __bf16 *__restrict__ W3t, const float *__restrict__ b1,
+                                                   const float *__restrict__ b2, const float *__restrict__ b3p,
+                                                   float *__restrict__ Y) {
+  __shared__ __attribute__((aligned(16))) __bf16 buf0[kRows * kLd];
+  __shared__ __attribute__((aligned(16))) __bf16 buf1[kRows * kLd];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int e0 = blockIdx.x * kRows;
+  for (int idx = tid; idx < kRows * kInPad; idx += 256) {
+    const int rr = idx / kInPad, k = idx - rr * kInPad;
+    const int e = e0 + rr < rows ? e0 + rr : rows - 1;
+    float x = 0.f;
+    if (k < kFeatures) {
+      if constexpr (FROM_Q) {
+        const int s = k / 12, vm = k - s * 12;
+        const int dj = s / 3 - 1, di = s % 3 - 1;
+        const int j = e / n_lon, i = e - j * n_lon;
+        int jj = j + dj;
+        jj = jj < 0 ? 0 : (jj >= n_lat ? n_lat - 1 : jj);
+        int ii = i + di;
+        ii = ii < 0 ? ii + n_lon : (ii >= n_lon ? ii - n_lon : ii);
+        x = ((float)q[((size_t)jj * n_lon + ii) * 12 + vm] - fmean[k]) * fistd[k];
+      } else {
+        x = X[(size_t)e * kFeatures + k];
+      }
+    }
+    buf0[rr * kLd + k] = (__bf16)x;
+  }
+  __syncthreads();
+  fused_hidden<kInPad>(W1t, b1, buf0, buf1, wv, lane);
+  __syncthreads();
+  fused_hidden<kHidden>(W2t, b2, buf1, buf0, wv, lane);
+  __syncthreads();
+  // output layer: wavefront wv takes rows [16 wv, 16 wv + 16), both 16-unit tiles
+  const int r = lane & 15, kq = (lane >> 4) * 8;
+  f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll 4
+  for (int k0 = 0; k0 < kHidden; k0 += 32) {
+    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(buf0 + (16 * wv + r) * kLd + k0 + kq);
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W3t + (size_t)(16 * nt + r) * kHidden + k0 + kq);
+      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nt], 0, 0, 0);
+    }
+  }
+  const int e = e0 + 16 * wv + r;
+  if (e < rows) {
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int n0 = 16 * nt + (lane >> 4) * 4;
+      const f32x4 bv = *reinterpret_cast<const f32x4 *>(b3p + n0);
+      *reinterpret_cast<f32x4 *>(Y + (size_t)e * kOutPad + n0) = acc[nt] + bv;
+    }
+  }
+}
+
+hipError_t launch_mlp_fused(int dtype, const void *q, int n_lon, int n_lat, const float *fmean, const float *fistd,
+                            const float *X, int rows, const __bf16 *W1t, const __bf16 *W2t, const __bf16 *W3t,
+                            const float *b1, const float *b2, const float *b3p, float *Y, hipStream_t s) {
+  static_assert(kInPad % 32 == 0 && kHidden == 256 && kOutPad == 32, "fused network shape");
+  if (rows <= 0) return hipSuccess;
+  const dim3 grid((rows + kRows - 1) / kRows), block(256);
+  if (!q)
+    hipLaunchKernelGGL((k_mlp_fused<float, false>), grid, block, 0, s, nullptr, 0, 0, nullptr, nullptr, X, rows, W1t,
+                       W2t, W3t, b1, b2, b3p, Y);
+  else if (dtype == 0)
+    hipLaunchKernelGGL((k_mlp_fused<double, true>), grid, block, 0, s, static_cast<const double *>(q), n_lon, n_lat,
+                       fmean, fistd, nullptr, rows, W1t, W2t, W3t, b1, b2, b3p, Y);
+  else
+    hipLaunchKernelGGL((k_mlp_fused<float, true>), grid, block, 0, s, static_cast<const float *>(q), n_lon, n_lat,
+                       fmean, fistd, nullptr, rows, W1t, W2t, W3t, b1, b2, b3p, Y);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ weights
 // FP32 parameter vector -> BF16 operand copies: Wt[n][kp] (forward, k
 // contiguous, k padded with zeros to kp) and Wr[k][np] (backward, rows padded

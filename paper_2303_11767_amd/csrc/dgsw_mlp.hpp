@@ -23,6 +23,12 @@ struct GemmArgs {
   int ldc;
 };
 hipError_t launch_gemm(bool a_kc, bool b_kc, int epi, const GemmArgs &g, hipStream_t s);
+// Whole-network inference, 64 rows per workgroup, activations in LDS: rows of
+// the stencil features of the r = 1 state q (dtype 0/1) or, with q == NULL,
+// of X[rows][108] (FP32).  Y[rows][32] FP32 (the first 12 used).
+hipError_t launch_mlp_fused(int dtype, const void *q, int n_lon, int n_lat, const float *fmean, const float *fistd,
+                            const float *X, int rows, const __bf16 *W1t, const __bf16 *W2t, const __bf16 *W3t,
+                            const float *b1, const float *b2, const float *b3p, float *Y, hipStream_t s);
 hipError_t launch_prep_weights(const float *W, int k_in, int n_out, int kp, int np_, __bf16 *Wt, __bf16 *Wr,
                                hipStream_t s);
 hipError_t launch_mse_grad(const float *Y, const float *T, const float *mask, int rows, int n_out, int ld, float scale,

@@ -270,7 +270,18 @@ def main():
     ap.add_argument("--t-eval", type=float, default=30.0)
     ap.add_argument("--out", default="learned_r1_360x180.npz")
     ap.add_argument("--report", default=None)
+    ap.add_argument("--judge-only", default=None, metavar="MODEL",
+                    help="judge a saved model (no training)")
     args = ap.parse_args()
+    if args.judge_only:
+        model, meta = load_model(args.judge_only)
+        report = judge(args, model, range(200, 200 + args.heldout), args.t_eval)
+        report["model"] = os.path.basename(args.judge_only)
+        log(json.dumps(report))
+        if args.report:
+            with open(args.report, "w") as f:
+                json.dump(report, f, indent=1)
+        return
     wb = Workbench("f32")
     t0 = time.time()
     X, T, stats = build_dataset(args, wb)

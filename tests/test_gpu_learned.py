@@ -216,6 +216,25 @@ def test_learned_rhs_fallback_and_mass(dg):
     assert abs(m_learn - m_plain) <= 1e-9 * scale
 
 
+def test_learned_rhs_matches_oracle(dg):
+    """The fused learned right-hand side end to end (features, network and
+    de-standardisation in the library) against the oracle network on the
+    same state: every correction entry but the global (h, mode 00) one."""
+    say("learned rhs vs oracle")
+    mesh, q, net = _learned_setup(dg, kappa=1e30)
+    got = (net.rhs(q) - mesh.rhs(q)).cpu().numpy().reshape(mesh.E, 12)
+    assert net.fallbacks.item() == 0
+    params, fmean, fistd, omean, ostd = (t.cpu().numpy().astype(np.float64) for t in net.tensors)
+    X = mlp.stencil_features(q.cpu().numpy(), mesh.n_lon, mesh.n_lat)
+    Xs = ((X - fmean) * fistd).astype(np.float32).astype(np.float64)
+    Y, _ = mlp.forward(unflat(params), Xs)
+    j = np.arange(mesh.E) // mesh.n_lon
+    ref = omean.reshape(-1, 12)[j] + ostd.reshape(-1, 12)[j] * Y
+    err = rel(got[:, 1:], ref[:, 1:])
+    say("  normwise", err)
+    assert err <= 3e-4
+
+
 def test_learned_rk_step_runs(dg):
     say("learned rk step")
     dgm, learned = dg
