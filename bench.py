@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 N_LON, N_LAT, ORDER, L_MAX, SEED, CFL = 180, 90, 3, 16, 2, 0.1
 HBM_PEAK_GBS = 8000.0
 METRIC = "DG RHS DOF-updates/s + % HBM roofline; learned r=1 vs plain r=4 at equal err"
-COUNTERS = os.path.join(ROOT, "profiles", "k_dg_stage_r3_180x90_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "k_dg_stage_r3_180x90.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2303_11767_amd", "csrc", "dgsw_kernels.hip")
 LEARNED_MODEL = os.path.join(ROOT, "paper_2303_11767_amd", "models", "learned_r1_360x180.npz")
 
@@ -251,9 +251,11 @@ def learned_section(model_path, seeds=(200, 201), t_eval=10.0):
     """The learned r = 1 form against plain r = 1 and plain r = 4, judged by
     the plain r = 5 solver (FP64, held-out seeds), with wall-clock."""
     import argparse as _ap
+    import contextlib
     from paper_2303_11767_amd import train_learned as tl
     model, meta = tl.load_model(model_path)
-    rep = tl.judge(_ap.Namespace(kappa=meta.get("kappa", 1.0)), model, seeds, t_eval)
+    with contextlib.redirect_stdout(sys.stderr):      # stdout carries only the JSON line
+        rep = tl.judge(_ap.Namespace(kappa=meta.get("kappa", 1.0)), model, seeds, t_eval)
     rep["model"] = os.path.relpath(model_path, ROOT)
     return rep
 
@@ -304,12 +306,17 @@ def profile_probe(args):
 
     import paper_2303_11767_amd as dg
     from dg_inputs import band_limited_state
-    q_h, info = band_limited_state(N_LON, N_LAT, ORDER, L_MAX, SEED)
+    n_lon, n_lat, order, lmax, seed = N_LON, N_LAT, ORDER, L_MAX, SEED
+    if args.probe_mesh:          # another mesh for counter runs: NLONxNLATxR (l <= 32, seed 5)
+        n_lon, n_lat, order = (int(v) for v in args.probe_mesh.split("x"))
+        lmax, seed = 32, 5
+    q_h, info = band_limited_state(n_lon, n_lat, order, lmax, seed)
     href = 1.0e4 if args.dtype == "f32" else 0.0
-    mesh = dg.Mesh(N_LON, N_LAT, ORDER, dtype=args.dtype, h_ref=href)
+    mesh = dg.Mesh(n_lon, n_lat, order, dtype=args.dtype, h_ref=href)
     q = torch.from_numpy(q_h).to(device="cuda", dtype=mesh.dtype).contiguous()
     work = mesh.empty_work()
     dt = dg.cfl_time_step(mesh, info.cmax, CFL)
+    mesh.rk_step(q, work, dt, nsteps=args.warmup)
     mesh.rk_step(q, work, dt, nsteps=args.steps)
     torch.cuda.synchronize()
     nbytes = 256 << 20
@@ -318,8 +325,9 @@ def profile_probe(args):
     for _ in range(5):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "done", "copy_bytes": nbytes, "stage_launches": 3 * args.steps}),
-          flush=True)
+    print(json.dumps({"probe": "done", "mesh": [n_lon, n_lat, order], "kernel": mesh.kernel,
+                      "state_bytes": q.numel() * q.element_size(), "copy_bytes": nbytes,
+                      "stage_launches": 3 * args.steps}), flush=True)
 
 
 def main():
@@ -335,6 +343,8 @@ def main():
                     help="skip the ensemble and learned-correction sections")
     ap.add_argument("--profile-probe", action="store_true",
                     help="short run for rocprofv3 counter passes (prints no bench line)")
+    ap.add_argument("--probe-mesh", default=None, metavar="NLONxNLATxR",
+                    help="mesh of the profile probe (default: the benchmark mesh)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -121,7 +121,7 @@ TrainWs carve_train(void *ws, int64_t rows, size_t *bytes) {
 struct LearnWs {
   Weights w;
   void *L1;
-  float *Y, *C, *delta;
+  float *C;
   double *partial;
 };
 
@@ -131,10 +131,8 @@ LearnWs carve_learn(void *ws, const dg_ctx *ctx, size_t *bytes) {
   const int64_t E = ctx->E;
   t.w = carve_weights(c, false);
   t.L1 = c.take<char>(E * 12 * ctx->elem_bytes);
-  t.Y = c.take<float>(E * kOutPad);
   t.C = c.take<float>(E * 12);
-  t.partial = c.take<double>((E + 255) / 256);
-  t.delta = c.take<float>(1);
+  t.partial = c.take<double>(dgsw::mlp_fused_blocks((int)E));
   if (bytes) *bytes = c.off;
   return t;
 }
@@ -173,7 +171,7 @@ int dg_mlp_forward(const float *params, const float *X, int64_t rows, float *Y, 
   hipError_t e;
   if ((e = prep(params, t.w, s)) != hipSuccess) return hip_fail(e, "weight preparation");
   if ((e = dgsw::launch_mlp_fused(0, nullptr, 0, 0, nullptr, nullptr, X, (int)rows, t.w.W1t, t.w.W2t, t.w.W3t,
-                                  params + ob1, params + ob2, t.w.b3p, t.Y, s)) != hipSuccess)
+                                  params + ob1, params + ob2, t.w.b3p, t.Y, s, nullptr)) != hipSuccess)
     return hip_fail(e, "forward");
   if ((e = dgsw::launch_unpad(t.Y, (int)rows, kOut, kOutPad, Y, s)) != hipSuccess) return hip_fail(e, "output");
   return DG_OK;
@@ -290,19 +288,23 @@ int learned_stage(dg_ctx *ctx, const dg_learned *net, const LearnWs &t, const vo
   a.q = q; a.q0 = nullptr; a.out = t.L1; a.forcing = ctx->forcing; a.glob = ctx->d_glob; a.rows = ctx->d_rows;
   a.n_lon = ctx->d.n_lon; a.n_lat = ctx->d.n_lat; a.E = ctx->E;
   a.alpha_global = ctx->d.alpha_mode == DG_ALPHA_GLOBAL; a.combine = 0; a.c0 = 0.0; a.c1 = 1.0; a.dt = 0.0;
+  a.periodic_y = ctx->periodic_y;
+  a.variant = ctx->kernel;        // the same kernel layout as dg_rhs on this context
   hipError_t e = dgsw::launch_stage(dt_, ctx->np, a, s);
   if (e != hipSuccess) return hip_fail(e, "r = 1 stage launch");
-  // features and the whole network in one launch (hidden layers in LDS)
+  // features, the whole network (hidden layers in LDS) and the per-element
+  // correction with its trust bound, in one launch
+  dgsw::CorrectionArgs ca;
+  ca.L1 = t.L1; ca.omean = net->out_mean; ca.ostd = net->out_std; ca.mass_w = ctx->d_mass_w;
+  ca.kappa = (float)net->kappa; ca.C = t.C; ca.partial = t.partial; ca.fallback = fallbacks;
   if ((e = dgsw::launch_mlp_fused(dt_, q, ctx->d.n_lon, ctx->d.n_lat, net->feat_mean, net->feat_istd, nullptr,
                                   ctx->E, t.w.W1t, t.w.W2t, t.w.W3t, net->params + ob1, net->params + ob2, t.w.b3p,
-                                  t.Y, s)) != hipSuccess)
+                                  nullptr, s, &ca)) != hipSuccess)
     return hip_fail(e, "network launch");
-  dgsw::LearnedLaunch l;
-  l.Y = t.Y; l.ldy = kOutPad; l.L1 = t.L1; l.omean = net->out_mean; l.ostd = net->out_std;
-  l.mass_w = ctx->d_mass_w; l.n_lon = ctx->d.n_lon; l.E = ctx->E; l.kappa = (float)net->kappa; l.C = t.C;
-  l.partial = t.partial; l.fallback = fallbacks; l.area = ctx->mass_area; l.delta = t.delta;
-  l.q = q; l.q0 = q0; l.out = out; l.combine = combine; l.c0 = c0; l.c1 = c1; l.dt = dt;
-  if ((e = dgsw::launch_correction(dt_, l, s)) != hipSuccess) return hip_fail(e, "correction launch");
+  dgsw::LearnedOut l;
+  l.L1 = t.L1; l.C = t.C; l.partial = t.partial; l.nparts = dgsw::mlp_fused_blocks(ctx->E); l.E = ctx->E;
+  l.area = ctx->mass_area; l.q = q; l.q0 = q0; l.out = out; l.combine = combine; l.c0 = c0; l.c1 = c1; l.dt = dt;
+  if ((e = dgsw::launch_learned_out(dt_, l, s)) != hipSuccess) return hip_fail(e, "output launch");
   return DG_OK;
 }
 

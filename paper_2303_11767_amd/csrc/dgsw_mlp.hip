@@ -21,9 +21,22 @@ namespace dgsw {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf by the rational approximation of Abramowitz & Stegun, formula 7.1.26
+// (Hastings): erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),
+// t = 1 / (1 + p x) for x >= 0, odd extension; absolute error <= 1.5e-7, far
+// below the BF16 rounding the activations then take.  Branch-free: one
+// hardware reciprocal and one hardware exponential.
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+  const float poly =
+      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+  const float r = fmaf(-poly, __expf(-ax * ax), 1.0f);
+  return copysignf(r, x);
+}
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad_f(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+  return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -128,7 +141,7 @@ hipError_t launch_gemm(bool a_kc, bool b_kc, int epi, const GemmArgs &g, hipStre
 }
 
 // ------------------------------------------------------------------ fused inference
-// The whole network on 64 rows per workgroup (4 wavefronts): the BF16 inputs
+// The whole network on 64 rows per workgroup (8 wavefronts): the BF16 inputs
 // (stencil features computed from an r = 1 state, or given FP32 rows) and
 // both hidden layers stay in LDS; only the weights (from L2) and the FP32
 // outputs touch global memory.  Each product is computed transposed,
@@ -138,49 +151,59 @@ hipError_t launch_gemm(bool a_kc, bool b_kc, int epi, const GemmArgs &g, hipStre
 // Same rounding points as the unfused path: BF16 inputs, weights and hidden
 // activations, FP32 accumulation, bias and GELU in FP32.
 constexpr int kRows = 64;                 // rows per workgroup
+template <typename T>
+struct MlpCorrection {           // the learned stage's correction step (FROM_Q)
+  const T *L1;
+  const float *omean, *ostd;
+  const double *mass_w;
+  float kappa;
+  float *C;
+  double *partial;
+  int *fallback;
+};
+constexpr int kWaves = 8;                 // wavefronts per workgroup
 constexpr int kLd = kHidden + 8;          // LDS row stride in BF16 (+16 B: no bank conflicts)
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 // One hidden layer for the 64 rows: wavefront wv computes units
-// [64 wv, 64 wv + 64) of out = gelu(in W^T + b), K inputs per row.
+// [32 wv, 32 wv + 32) of out = gelu(in W^T + b), K inputs per row; the
+// weight fragments are fetched two k-steps ahead.
 template <int K>
 __device__ __forceinline__ void fused_hidden(const __bf16 *__restrict__ Wt, const float *__restrict__ bias,
                                              const __bf16 *in, __bf16 *out, int wv, int lane) {
+  constexpr int NT = 2, MT = kRows / 16, KS = K / 32;
   const int r = lane & 15, kq = (lane >> 4) * 8;
-  f32x4 acc[4][4];
+  f32x4 acc[NT][MT];
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt)
+  for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const __bf16 *wrow[4];
+    for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const __bf16 *wrow[NT];
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) wrow[nt] = Wt + (size_t)(64 * wv + 16 * nt + r) * K + kq;
-  bf16x8 a[4];
+  for (int nt = 0; nt < NT; ++nt) wrow[nt] = Wt + (size_t)(32 * wv + 16 * nt + r) * K + kq;
+  bf16x8 a[KS][NT];
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) a[nt] = *reinterpret_cast<const bf16x8 *>(wrow[nt]);
-#pragma unroll 2
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    bf16x8 an[4];
-    const int kn = k0 + 32 < K ? k0 + 32 : k0;          // prefetch of the next weights
+  for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) an[nt] = *reinterpret_cast<const bf16x8 *>(wrow[nt] + kn);
-    bf16x8 b[4];
+    for (int nt = 0; nt < NT; ++nt) a[ks][nt] = *reinterpret_cast<const bf16x8 *>(wrow[nt] + 32 * ks);
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) b[mt] = *reinterpret_cast<const bf16x8 *>(in + (16 * mt + r) * kLd + k0 + kq);
+  for (int ks = 0; ks < KS; ++ks) {
+    bf16x8 b[MT];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int mt = 0; mt < MT; ++mt)
+      b[mt] = *reinterpret_cast<const bf16x8 *>(in + (16 * mt + r) * kLd + 32 * ks + kq);
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-        acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[nt], b[mt], acc[nt][mt], 0, 0, 0);
+    for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) a[nt] = an[nt];
+      for (int mt = 0; mt < MT; ++mt)
+        acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks][nt], b[mt], acc[nt][mt], 0, 0, 0);
   }
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
-    const int n0 = 64 * wv + 16 * nt + (lane >> 4) * 4;
+  for (int nt = 0; nt < NT; ++nt) {
+    const int n0 = 32 * wv + 16 * nt + (lane >> 4) * 4;
     const f32x4 bv = *reinterpret_cast<const f32x4 *>(bias + n0);
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
+    for (int mt = 0; mt < MT; ++mt) {
       bf16x4 h;
 #pragma unroll
       for (int i = 0; i < 4; ++i) h[i] = (__bf16)gelu_f(acc[nt][mt][i] + bv[i]);
@@ -189,83 +212,160 @@ __device__ __forceinline__ void fused_hidden(const __bf16 *__restrict__ Wt, cons
   }
 }
 
-// FROM_Q: features of the r = 1 state q (as k_features); else rows of X[rows][108].
+// Per-element correction from the network output y[12] (standardised), as
+// k_correction: c = mean_j + std_j y with c_(h,00) = 0; rejected (c = 0) if
+// non-finite or, for a variable, max|c| > kappa max|L1|.  Returns whether it
+// fell back and the element's h-mass of the correction.
+template <typename T>
+__device__ __forceinline__ bool correction_row(const float *y, const T *__restrict__ L1e, const float *__restrict__ om,
+                                               const float *__restrict__ os, float kappa, float *c) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    c[k] = k == 0 ? 0.f : om[k] + os[k] * y[k];
+    ok = ok && isfinite(c[k]);
+  }
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    float mc = 0.f, ml = 0.f;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      mc = fmaxf(mc, fabsf(c[v * 4 + m]));
+      ml = fmaxf(ml, fabsf((float)L1e[v * 4 + m]));
+    }
+    ok = ok && !(mc > kappa * ml);
+  }
+  if (!ok) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) c[k] = 0.f;
+  }
+  return !ok;
+}
+
+// FROM_Q: features of the r = 1 state q (as k_features), then the correction
+// of every element (the learned stage): C[rows][12], the workgroup's h-mass
+// of the corrections in partial[blockIdx.x] and the fallback count; else the
+// network on rows of X[rows][108], output Y[rows][32].
 template <typename T, bool FROM_Q>
-__global__ __launch_bounds__(256) void k_mlp_fused(const T *__restrict__ q, int n_lon, int n_lat,
-                                                   const float *__restrict__ fmean, const float *__restrict__ fistd,
-                                                   const float *__restrict__ X, int rows,
-                                                   const __bf16 *__restrict__ W1t, const __bf16 *__restrict__ W2t,
-                                                   const __bf16 *__restrict__ W3t, const float *__restrict__ b1,
-                                                   const float *__restrict__ b2, const float *__restrict__ b3p,
-                                                   float *__restrict__ Y) {
+__global__ __launch_bounds__(64 * kWaves) void k_mlp_fused(const T *__restrict__ q, int n_lon, int n_lat,
+                                                          const float *__restrict__ fmean,
+                                                          const float *__restrict__ fistd,
+                                                          const float *__restrict__ X, int rows,
+                                                          const __bf16 *__restrict__ W1t,
+                                                          const __bf16 *__restrict__ W2t,
+                                                          const __bf16 *__restrict__ W3t,
+                                                          const float *__restrict__ b1, const float *__restrict__ b2,
+                                                          const float *__restrict__ b3p, float *__restrict__ Y,
+                                                          MlpCorrection<T> cor) {
   __shared__ __attribute__((aligned(16))) __bf16 buf0[kRows * kLd];
   __shared__ __attribute__((aligned(16))) __bf16 buf1[kRows * kLd];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int e0 = blockIdx.x * kRows;
-  for (int idx = tid; idx < kRows * kInPad; idx += 256) {
-    const int rr = idx / kInPad, k = idx - rr * kInPad;
+  // inputs: one task per (row, stencil neighbour): 12 contiguous values
+  for (int idx = tid; idx < kRows * (kInPad - kFeatures); idx += 64 * kWaves) {
+    const int rr = idx / (kInPad - kFeatures);
+    buf0[rr * kLd + kFeatures + (idx - rr * (kInPad - kFeatures))] = (__bf16)0.f;
+  }
+  for (int task = tid; task < kRows * 9; task += 64 * kWaves) {
+    const int rr = task / 9, sn = task - rr * 9;
     const int e = e0 + rr < rows ? e0 + rr : rows - 1;
-    float x = 0.f;
-    if (k < kFeatures) {
-      if constexpr (FROM_Q) {
-        const int s = k / 12, vm = k - s * 12;
-        const int dj = s / 3 - 1, di = s % 3 - 1;
-        const int j = e / n_lon, i = e - j * n_lon;
-        int jj = j + dj;
-        jj = jj < 0 ? 0 : (jj >= n_lat ? n_lat - 1 : jj);
-        int ii = i + di;
-        ii = ii < 0 ? ii + n_lon : (ii >= n_lon ? ii - n_lon : ii);
-        x = ((float)q[((size_t)jj * n_lon + ii) * 12 + vm] - fmean[k]) * fistd[k];
-      } else {
-        x = X[(size_t)e * kFeatures + k];
-      }
+    float x[12];
+    if constexpr (FROM_Q) {
+      const int dj = sn / 3 - 1, di = sn % 3 - 1;
+      const int j = e / n_lon, i = e - j * n_lon;
+      int jj = j + dj;
+      jj = jj < 0 ? 0 : (jj >= n_lat ? n_lat - 1 : jj);
+      int ii = i + di;
+      ii = ii < 0 ? ii + n_lon : (ii >= n_lon ? ii - n_lon : ii);
+      const T *src = q + ((size_t)jj * n_lon + ii) * 12;
+#pragma unroll
+      for (int vm = 0; vm < 12; ++vm) x[vm] = (float)src[vm];
+#pragma unroll
+      for (int vm = 0; vm < 12; ++vm) x[vm] = (x[vm] - fmean[sn * 12 + vm]) * fistd[sn * 12 + vm];
+    } else {
+      const float *src = X + (size_t)e * kFeatures + sn * 12;
+#pragma unroll
+      for (int vm = 0; vm < 12; ++vm) x[vm] = src[vm];
     }
-    buf0[rr * kLd + k] = (__bf16)x;
+#pragma unroll
+    for (int vm = 0; vm < 12; ++vm) buf0[rr * kLd + sn * 12 + vm] = (__bf16)x[vm];
   }
   __syncthreads();
   fused_hidden<kInPad>(W1t, b1, buf0, buf1, wv, lane);
   __syncthreads();
   fused_hidden<kHidden>(W2t, b2, buf1, buf0, wv, lane);
   __syncthreads();
-  // output layer: wavefront wv takes rows [16 wv, 16 wv + 16), both 16-unit tiles
+  // output layer: wavefront wv takes rows [16 (wv / 2), +16) and units [16 (wv % 2), +16)
   const int r = lane & 15, kq = (lane >> 4) * 8;
-  f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll 4
+  const int mt = wv >> 1, nt = wv & 1;
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
   for (int k0 = 0; k0 < kHidden; k0 += 32) {
-    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(buf0 + (16 * wv + r) * kLd + k0 + kq);
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W3t + (size_t)(16 * nt + r) * kHidden + k0 + kq);
-      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nt], 0, 0, 0);
-    }
+    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(buf0 + (16 * mt + r) * kLd + k0 + kq);
+    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W3t + (size_t)(16 * nt + r) * kHidden + k0 + kq);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
   }
-  const int e = e0 + 16 * wv + r;
-  if (e < rows) {
+  const int n0 = 16 * nt + (lane >> 4) * 4;
+  const f32x4 out = acc + *reinterpret_cast<const f32x4 *>(b3p + n0);
+  if constexpr (!FROM_Q) {
+    const int e = e0 + 16 * mt + r;
+    if (e < rows) *reinterpret_cast<f32x4 *>(Y + (size_t)e * kOutPad + n0) = out;
+  } else {
+    // outputs to LDS (the first hidden layer's buffer is free), then one lane
+    // per row forms its element's correction; wavefront 0 does all 64 rows
+    float *ys = reinterpret_cast<float *>(buf1);
+    *reinterpret_cast<f32x4 *>(ys + (16 * mt + r) * kOutPad + n0) = out;
+    __syncthreads();
+    if (wv == 0) {
+      const int e = e0 + lane;
+      double mass = 0.0;
+      bool fell = false;
+      if (e < rows) {
+        const int j = e / n_lon;
+        float c[12];
+        fell = correction_row<T>(ys + lane * kOutPad, cor.L1 + (size_t)e * 12, cor.omean + j * 12,
+                                 cor.ostd + j * 12, cor.kappa, c);
+        // h-mass of the correction: modes (a, b) = (0, 0) and (0, 1), i.e. 0 and 2
+        mass = cor.mass_w[j * 2 + 1] * (double)c[2];
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      const int n0 = 16 * nt + (lane >> 4) * 4;
-      const f32x4 bv = *reinterpret_cast<const f32x4 *>(b3p + n0);
-      *reinterpret_cast<f32x4 *>(Y + (size_t)e * kOutPad + n0) = acc[nt] + bv;
+        for (int k = 0; k < 12; ++k) cor.C[(size_t)e * 12 + k] = c[k];
+      }
+      const unsigned long long fb = __ballot(fell);
+      if (cor.fallback && lane == 0 && fb != 0ull) atomicAdd(cor.fallback, (int)__popcll(fb));
+      // fixed-order (tree) wavefront sum of the 64 rows' masses
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) mass += __shfl_down(mass, off, 64);
+      if (lane == 0) cor.partial[blockIdx.x] = mass;
     }
   }
 }
 
 hipError_t launch_mlp_fused(int dtype, const void *q, int n_lon, int n_lat, const float *fmean, const float *fistd,
                             const float *X, int rows, const __bf16 *W1t, const __bf16 *W2t, const __bf16 *W3t,
-                            const float *b1, const float *b2, const float *b3p, float *Y, hipStream_t s) {
-  static_assert(kInPad % 32 == 0 && kHidden == 256 && kOutPad == 32, "fused network shape");
+                            const float *b1, const float *b2, const float *b3p, float *Y, hipStream_t s,
+                            const CorrectionArgs *ca) {
+  static_assert(kInPad % 32 == 0 && kHidden == 32 * kWaves && kOutPad == 32 && kRows == 8 * kWaves,
+                "fused network shape");
   if (rows <= 0) return hipSuccess;
-  const dim3 grid((rows + kRows - 1) / kRows), block(256);
-  if (!q)
+  const dim3 grid((rows + kRows - 1) / kRows), block(64 * kWaves);
+  if (!q) {
     hipLaunchKernelGGL((k_mlp_fused<float, false>), grid, block, 0, s, nullptr, 0, 0, nullptr, nullptr, X, rows, W1t,
-                       W2t, W3t, b1, b2, b3p, Y);
-  else if (dtype == 0)
+                       W2t, W3t, b1, b2, b3p, Y, MlpCorrection<float>{});
+    return hipGetLastError();
+  }
+  if (!ca) return hipErrorInvalidValue;
+  if (dtype == 0) {
+    MlpCorrection<double> c{static_cast<const double *>(ca->L1), ca->omean, ca->ostd, ca->mass_w, ca->kappa, ca->C,
+                            ca->partial, ca->fallback};
     hipLaunchKernelGGL((k_mlp_fused<double, true>), grid, block, 0, s, static_cast<const double *>(q), n_lon, n_lat,
-                       fmean, fistd, nullptr, rows, W1t, W2t, W3t, b1, b2, b3p, Y);
-  else
+                       fmean, fistd, nullptr, rows, W1t, W2t, W3t, b1, b2, b3p, Y, c);
+  } else {
+    MlpCorrection<float> c{static_cast<const float *>(ca->L1), ca->omean, ca->ostd, ca->mass_w, ca->kappa, ca->C,
+                           ca->partial, ca->fallback};
     hipLaunchKernelGGL((k_mlp_fused<float, true>), grid, block, 0, s, static_cast<const float *>(q), n_lon, n_lat,
-                       fmean, fistd, nullptr, rows, W1t, W2t, W3t, b1, b2, b3p, Y);
+                       fmean, fistd, nullptr, rows, W1t, W2t, W3t, b1, b2, b3p, Y, c);
+  }
   return hipGetLastError();
 }
 
@@ -497,63 +597,11 @@ hipError_t launch_features(int dtype, const void *q, int n_lon, int n_lat, const
 }
 
 // ------------------------------------------------------------------ learned stage
-// Correction of element e from the network output Y[e][0..11] (standardised):
-// c = mean_j + std_j * Y; rejected (c = 0, counted) if non-finite or if, for
-// some variable, max |c| > kappa max |L1| over its 4 modes.  The (h, mode 00)
-// output is not predicted: it is set by the global mass correction.  Block
-// partial sums of the element masses of the h-correction go to partial[].
-template <typename T>
-__global__ __launch_bounds__(256) void k_correction(const float *__restrict__ Y, int ldy, const T *__restrict__ L1,
-                                                    const float *__restrict__ omean, const float *__restrict__ ostd,
-                                                    const double *__restrict__ mass_w, int n_lon, int E, float kappa,
-                                                    float *__restrict__ C, double *__restrict__ partial,
-                                                    int *__restrict__ fallback) {
-  __shared__ double sh[256];
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  double mass = 0.0;
-  if (e < E) {
-    const int j = e / n_lon;
-    float c[12];
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      c[k] = k == 0 ? 0.f : omean[j * 12 + k] + ostd[j * 12 + k] * Y[(size_t)e * ldy + k];
-      ok = ok && isfinite(c[k]);
-    }
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      float mc = 0.f, ml = 0.f;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        mc = fmaxf(mc, fabsf(c[v * 4 + m]));
-        ml = fmaxf(ml, fabsf((float)L1[(size_t)e * 12 + v * 4 + m]));
-      }
-      ok = ok && !(mc > kappa * ml);
-    }
-    if (!ok) {
-#pragma unroll
-      for (int k = 0; k < 12; ++k) c[k] = 0.f;
-      if (fallback) atomicAdd(fallback, 1);
-    }
-    // element mass of the h-correction: modes (a = 0, b = 0) and (a = 0, b = 1) = 0 and 2
-    mass = mass_w[j * 2 + 1] * (double)c[2];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) C[(size_t)e * 12 + k] = c[k];
-  }
-  sh[threadIdx.x] = mass;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
-}
-
 // delta = -(sum of partials) / (sum over elements of mass_w[j][0]): the mode-00
 // h-correction that makes the total h-mass change of the correction zero.
-__global__ __launch_bounds__(256) void k_mass_delta(const double *__restrict__ partial, int nparts,
-                                                    double area, float *__restrict__ delta) {
-  __shared__ double sh[256];
+// Every block of the output kernel forms it itself, in the same fixed order.
+__device__ __forceinline__ float block_mass_delta(const double *__restrict__ partial, int nparts, double area,
+                                                  double *sh) {
   double acc = 0.0;
   for (int k = threadIdx.x; k < nparts; k += 256) acc += partial[k];
   sh[threadIdx.x] = acc;
@@ -562,7 +610,7 @@ __global__ __launch_bounds__(256) void k_mass_delta(const double *__restrict__ p
     if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *delta = (float)(-sh[0] / area);
+  return (float)(-sh[0] / area);
 }
 
 // out = combine ? c0 q0 + c1 (q + dt (L1 + c)) : L1 + c, with c_(h,00) = delta;
@@ -570,12 +618,15 @@ __global__ __launch_bounds__(256) void k_mass_delta(const double *__restrict__ p
 // ce = c0 + c1 - 1 formed in FP64, so the weights sum to one exactly.
 template <typename T>
 __global__ __launch_bounds__(256) void k_learned_out(const T *__restrict__ q, const T *q0, const T *__restrict__ L1,
-                                                     const float *__restrict__ C, const float *__restrict__ delta,
-                                                     int E, int combine, T c0, T ce, T dt, T *out) {
+                                                     const float *__restrict__ C, const double *__restrict__ partial,
+                                                     int nparts, double area, int E, int combine, T c0, T ce, T dt,
+                                                     T *out) {
+  __shared__ double sh[256];
+  const float delta = block_mass_delta(partial, nparts, area, sh);
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= E * 12) return;
   const int k = idx % 12;
-  const T corr = k == 0 ? (T)(*delta) : (T)C[idx];
+  const T corr = k == 0 ? (T)delta : (T)C[idx];
   const T l = L1[idx] + corr;
   if (combine) {
     const T qn = c0 != T(0) ? q0[idx] : T(0);
@@ -586,30 +637,16 @@ __global__ __launch_bounds__(256) void k_learned_out(const T *__restrict__ q, co
   }
 }
 
-hipError_t launch_correction(int dtype, const LearnedLaunch &a, hipStream_t s) {
-  const int blocks = (a.E + 255) / 256;
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_correction<double>, dim3(blocks), dim3(256), 0, s, a.Y, a.ldy,
-                       static_cast<const double *>(a.L1), a.omean, a.ostd, a.mass_w, a.n_lon, a.E, a.kappa, a.C,
-                       a.partial, a.fallback);
-  else
-    hipLaunchKernelGGL(k_correction<float>, dim3(blocks), dim3(256), 0, s, a.Y, a.ldy,
-                       static_cast<const float *>(a.L1), a.omean, a.ostd, a.mass_w, a.n_lon, a.E, a.kappa, a.C,
-                       a.partial, a.fallback);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_mass_delta, dim3(1), dim3(256), 0, s, a.partial, blocks, a.area, a.delta);
-  err = hipGetLastError();
-  if (err != hipSuccess) return err;
+hipError_t launch_learned_out(int dtype, const LearnedOut &a, hipStream_t s) {
   const int ob = (a.E * 12 + 255) / 256;
   if (dtype == 0)
     hipLaunchKernelGGL(k_learned_out<double>, dim3(ob), dim3(256), 0, s, static_cast<const double *>(a.q),
-                       static_cast<const double *>(a.q0), static_cast<const double *>(a.L1), a.C, a.delta, a.E,
-                       a.combine, a.c0, a.c0 + a.c1 - 1.0, a.dt, static_cast<double *>(a.out));
+                       static_cast<const double *>(a.q0), static_cast<const double *>(a.L1), a.C, a.partial, a.nparts,
+                       a.area, a.E, a.combine, a.c0, a.c0 + a.c1 - 1.0, a.dt, static_cast<double *>(a.out));
   else
     hipLaunchKernelGGL(k_learned_out<float>, dim3(ob), dim3(256), 0, s, static_cast<const float *>(a.q),
-                       static_cast<const float *>(a.q0), static_cast<const float *>(a.L1), a.C, a.delta, a.E,
-                       a.combine, (float)a.c0, (float)(a.c0 + a.c1 - 1.0), (float)a.dt,
+                       static_cast<const float *>(a.q0), static_cast<const float *>(a.L1), a.C, a.partial, a.nparts,
+                       a.area, a.E, a.combine, (float)a.c0, (float)(a.c0 + a.c1 - 1.0), (float)a.dt,
                        static_cast<float *>(a.out));
   return hipGetLastError();
 }

@@ -23,12 +23,25 @@ struct GemmArgs {
   int ldc;
 };
 hipError_t launch_gemm(bool a_kc, bool b_kc, int epi, const GemmArgs &g, hipStream_t s);
-// Whole-network inference, 64 rows per workgroup, activations in LDS: rows of
-// the stencil features of the r = 1 state q (dtype 0/1) or, with q == NULL,
-// of X[rows][108] (FP32).  Y[rows][32] FP32 (the first 12 used).
+// The learned stage's correction step, fused into the network kernel.
+struct CorrectionArgs {
+  const void *L1;                // plain r = 1 right-hand side [E][12] (state dtype)
+  const float *omean, *ostd;     // [n_lat][12]
+  const double *mass_w;          // [n_lat][2]
+  float kappa;
+  float *C;                      // corrections [E][12]
+  double *partial;               // one h-mass per workgroup: mlp_fused_blocks(E)
+  int *fallback;                 // optional device counter
+};
+inline int mlp_fused_blocks(int rows) { return (rows + 63) / 64; }
+// Whole-network inference, 64 rows per workgroup, activations in LDS.  With q:
+// rows = elements of the r = 1 state q (dtype 0/1), features computed from q,
+// then the correction of each element (ca required; Y unused).  With q == NULL:
+// rows of X[rows][108] (FP32) -> Y[rows][32] FP32 (the first 12 used).
 hipError_t launch_mlp_fused(int dtype, const void *q, int n_lon, int n_lat, const float *fmean, const float *fistd,
                             const float *X, int rows, const __bf16 *W1t, const __bf16 *W2t, const __bf16 *W3t,
-                            const float *b1, const float *b2, const float *b3p, float *Y, hipStream_t s);
+                            const float *b1, const float *b2, const float *b3p, float *Y, hipStream_t s,
+                            const CorrectionArgs *ca);
 hipError_t launch_prep_weights(const float *W, int k_in, int n_out, int kp, int np_, __bf16 *Wt, __bf16 *Wr,
                                hipStream_t s);
 hipError_t launch_mse_grad(const float *Y, const float *T, const float *mask, int rows, int n_out, int ld, float scale,
@@ -47,24 +60,20 @@ hipError_t launch_features_f32(int dtype, const void *q, int n_lon, int n_lat, c
 hipError_t launch_project1(int dtype, const void *q, int n_lon, int E, int np, const double *P, void *out,
                            hipStream_t s);
 
-struct LearnedLaunch {
-  const float *Y;        // network output, [E][ldy] standardised
-  int ldy;
+// The learned stage's last step: out = L1 + C, the (h, 00) entry replaced by
+// the global h-mass delta formed from the per-workgroup partials, or the
+// Runge-Kutta combination with it.
+struct LearnedOut {
   const void *L1;        // plain r = 1 right-hand side [E][12]
-  const float *omean, *ostd;   // [n_lat][12]
-  const double *mass_w;  // [n_lat][2]
-  int n_lon, E;
-  float kappa;
-  float *C;              // corrections [E][12]
-  double *partial;       // ceil(E / 256)
-  int *fallback;         // optional device counter
+  const float *C;        // corrections [E][12]
+  const double *partial; // nparts per-workgroup h-masses of the corrections
+  int nparts, E;
   double area;           // sum over elements of mass_w[j][0]
-  float *delta;          // device scalar
   const void *q, *q0;
   void *out;
   int combine;
   double c0, c1, dt;
 };
-hipError_t launch_correction(int dtype, const LearnedLaunch &a, hipStream_t s);
+hipError_t launch_learned_out(int dtype, const LearnedOut &a, hipStream_t s);
 
 }  // namespace dgsw

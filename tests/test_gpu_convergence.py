@@ -81,7 +81,7 @@ def test_manufactured_steady_state_converges(dg, order):
     for n_lat in (8, 16, 32):
         n_lon = 2 * n_lat
         m = SphereDG(n_lon, n_lat, order)
-        q0 = m.project(_q_exact)
+        q0 = np.ascontiguousarray(m.project(_q_exact))
         f = m.weak_forcing(_forcing_density)
         mesh = dg.Mesh(n_lon, n_lat, order, dtype="f64")
         qd = torch.from_numpy(q0).cuda()
