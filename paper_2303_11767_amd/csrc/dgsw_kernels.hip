@@ -900,7 +900,7 @@ constexpr int lds_sh(int k) {
 constexpr int lds_max_tab(int npmax) { return npmax == 0 ? 0 : (lds_tab(npmax) > lds_max_tab(npmax - 1) ? lds_tab(npmax) : lds_max_tab(npmax - 1)); }
 constexpr int lds_max_sh(int npmax) { return npmax == 0 ? 0 : (lds_sh(npmax) > lds_max_sh(npmax - 1) ? lds_sh(npmax) : lds_max_sh(npmax - 1)); }
 
-template <typename T, int NP>
+template <typename T, int NP, int CM>
 __device__ __forceinline__ void ens_case(const EnsItem &m, const T *q, const T *q0, T *out,
                                          int combine, T c0, T ce, int lane, T *tab, T *sh) {
   StageArgs<T, NP> A;
@@ -921,7 +921,7 @@ __device__ __forceinline__ void ens_case(const EnsItem &m, const T *q, const T *
   A.c1 = T(0);
   A.ce = ce;
   A.dt = T(m.dt);
-  stage_wave<T, NP, CM_RUNTIME>(A, m.j, m.seg, lane, tab, sh);
+  stage_wave<T, NP, CM>(A, m.j, m.seg, lane, tab, sh);
 }
 
 // One launch per Runge-Kutta stage for a whole ensemble of meshes of different
@@ -931,7 +931,7 @@ __device__ __forceinline__ void ens_case(const EnsItem &m, const T *q, const T *
 // contiguous item range [bounds[b], bounds[b+1]), balanced by cost on the host;
 // its WPB wavefronts take every WPB-th item.  The order of each member is a
 // wave-uniform switch.
-template <typename T, int NPMAX, int WPB>
+template <typename T, int NPMAX, int WPB, int CM>
 __global__ __launch_bounds__(64 * WPB) void k_ens_stage(const T *__restrict__ q, const T *q0, T *out,
                                                         const EnsItem *__restrict__ items,
                                                         const int *__restrict__ bounds, int combine,
@@ -945,17 +945,17 @@ __global__ __launch_bounds__(64 * WPB) void k_ens_stage(const T *__restrict__ q,
   for (int it = bounds[part] + wv; it < end; it += WPB) {
     const EnsItem m = items[it];
     switch (m.np) {
-      case 1: ens_case<T, 1>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
-      case 2: ens_case<T, 2>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
-      case 3: ens_case<T, 3>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
-      case 4: ens_case<T, 4>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
-      case 5: ens_case<T, 5>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 1: ens_case<T, 1, CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 2: ens_case<T, 2, CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 3: ens_case<T, 3, CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 4: ens_case<T, 4, CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 5: ens_case<T, 5, CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
       default:
         if constexpr (NPMAX > 5) {
           switch (m.np) {
-            case 6: ens_case<T, (NPMAX > 5 ? 6 : 1)>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
-            case 7: ens_case<T, (NPMAX > 6 ? 7 : 1)>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
-            case 8: ens_case<T, (NPMAX > 7 ? 8 : 1)>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+            case 6: ens_case<T, (NPMAX > 5 ? 6 : 1), CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+            case 7: ens_case<T, (NPMAX > 6 ? 7 : 1), CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+            case 8: ens_case<T, (NPMAX > 7 ? 8 : 1), CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
             default: break;
           }
         }
@@ -967,7 +967,7 @@ __global__ __launch_bounds__(64 * WPB) void k_ens_stage(const T *__restrict__ q,
 // Ensemble stage restricted to the members of one order (the work list is
 // sorted by order; bounds cover this order's items): the kernel is compiled for
 // that order alone, so it keeps that order's register budget and occupancy.
-template <typename T, int NP, int WPB>
+template <typename T, int NP, int WPB, int CM>
 __global__ __launch_bounds__(64 * WPB) void k_ens_stage_np(const T *__restrict__ q, const T *q0, T *out,
                                                            const EnsItem *__restrict__ items,
                                                            const int *__restrict__ bounds, int combine,
@@ -979,14 +979,14 @@ __global__ __launch_bounds__(64 * WPB) void k_ens_stage_np(const T *__restrict__
   const int end = bounds[part + 1];
   for (int it = bounds[part] + wv; it < end; it += WPB) {
     const EnsItem m = items[it];
-    ens_case<T, NP>(m, q, q0, out, combine, c0, ce, lane, tab_all[wv], sh_all[wv]);
+    ens_case<T, NP, CM>(m, q, q0, out, combine, c0, ce, lane, tab_all[wv], sh_all[wv]);
   }
 }
 
 // Flat form: workgroup b takes items begin + b*WPB + wv, one item per
 // wavefront, so the hardware schedules the ensemble like an ordinary grid
 // (no loop: same register budget as the single-mesh kernel).
-template <typename T, int NP, int WPB>
+template <typename T, int NP, int WPB, int CM>
 __global__ __launch_bounds__(64 * WPB) void k_ens_stage_flat(const T *__restrict__ q, const T *q0, T *out,
                                                              const EnsItem *__restrict__ items,
                                                              int begin, int end, int combine, T c0, T ce) {
@@ -996,23 +996,36 @@ __global__ __launch_bounds__(64 * WPB) void k_ens_stage_flat(const T *__restrict
   const int it = begin + xcd_block(blockIdx.x, gridDim.x) * WPB + wv;
   if (it >= end) return;
   const EnsItem m = items[it];
-  ens_case<T, NP>(m, q, q0, out, combine, c0, ce, lane, tab_all[wv], sh_all[wv]);
+  ens_case<T, NP, CM>(m, q, q0, out, combine, c0, ce, lane, tab_all[wv], sh_all[wv]);
 }
 
+// the combination mode is a template parameter of the ensemble kernels too:
+// 0 (right-hand side) or 1 (Shu-Osher stage)
 template <typename T, int NP, int WPB>
 static hipError_t launch_ens_flat_t(const EnsLaunch &a, hipStream_t s) {
   const int n = a.end - a.begin;
-  hipLaunchKernelGGL((k_ens_stage_flat<T, NP, WPB>), dim3((n + WPB - 1) / WPB), dim3(64 * WPB), 0, s,
-                     static_cast<const T *>(a.q), static_cast<const T *>(a.q0),
-                     static_cast<T *>(a.out), a.items, a.begin, a.end, a.combine, T(a.c0), T(a.c0 + a.c1 - 1.0));
+  const dim3 grid((n + WPB - 1) / WPB), block(64 * WPB);
+  if (a.combine)
+    hipLaunchKernelGGL((k_ens_stage_flat<T, NP, WPB, 1>), grid, block, 0, s, static_cast<const T *>(a.q),
+                       static_cast<const T *>(a.q0), static_cast<T *>(a.out), a.items, a.begin, a.end, 1, T(a.c0),
+                       T(a.c0 + a.c1 - 1.0));
+  else
+    hipLaunchKernelGGL((k_ens_stage_flat<T, NP, WPB, 0>), grid, block, 0, s, static_cast<const T *>(a.q),
+                       static_cast<const T *>(a.q0), static_cast<T *>(a.out), a.items, a.begin, a.end, 0, T(a.c0),
+                       T(a.c0 + a.c1 - 1.0));
   return hipGetLastError();
 }
 
 template <typename T, int NP, int WPB>
 static hipError_t launch_ens_np_t(const EnsLaunch &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_ens_stage_np<T, NP, WPB>), dim3(a.parts), dim3(64 * WPB), 0, s,
-                     static_cast<const T *>(a.q), static_cast<const T *>(a.q0),
-                     static_cast<T *>(a.out), a.items, a.bounds, a.combine, T(a.c0), T(a.c0 + a.c1 - 1.0));
+  if (a.combine)
+    hipLaunchKernelGGL((k_ens_stage_np<T, NP, WPB, 1>), dim3(a.parts), dim3(64 * WPB), 0, s,
+                       static_cast<const T *>(a.q), static_cast<const T *>(a.q0), static_cast<T *>(a.out), a.items,
+                       a.bounds, 1, T(a.c0), T(a.c0 + a.c1 - 1.0));
+  else
+    hipLaunchKernelGGL((k_ens_stage_np<T, NP, WPB, 0>), dim3(a.parts), dim3(64 * WPB), 0, s,
+                       static_cast<const T *>(a.q), static_cast<const T *>(a.q0), static_cast<T *>(a.out), a.items,
+                       a.bounds, 0, T(a.c0), T(a.c0 + a.c1 - 1.0));
   return hipGetLastError();
 }
 
@@ -1041,9 +1054,14 @@ hipError_t launch_ens_stage_np(int dtype, int np, int wpb, const EnsLaunch &a, h
 
 template <typename T, int NPMAX, int WPB>
 static hipError_t launch_ens_t(const EnsLaunch &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_ens_stage<T, NPMAX, WPB>), dim3(a.parts), dim3(64 * WPB), 0, s,
-                     static_cast<const T *>(a.q), static_cast<const T *>(a.q0),
-                     static_cast<T *>(a.out), a.items, a.bounds, a.combine, T(a.c0), T(a.c0 + a.c1 - 1.0));
+  if (a.combine)
+    hipLaunchKernelGGL((k_ens_stage<T, NPMAX, WPB, 1>), dim3(a.parts), dim3(64 * WPB), 0, s,
+                       static_cast<const T *>(a.q), static_cast<const T *>(a.q0), static_cast<T *>(a.out), a.items,
+                       a.bounds, 1, T(a.c0), T(a.c0 + a.c1 - 1.0));
+  else
+    hipLaunchKernelGGL((k_ens_stage<T, NPMAX, WPB, 0>), dim3(a.parts), dim3(64 * WPB), 0, s,
+                       static_cast<const T *>(a.q), static_cast<const T *>(a.q0), static_cast<T *>(a.out), a.items,
+                       a.bounds, 0, T(a.c0), T(a.c0 + a.c1 - 1.0));
   return hipGetLastError();
 }
 
