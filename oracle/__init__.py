@@ -10,6 +10,9 @@ and this package imports nothing from the product.
 ``plane`` is the same scheme on the doubly periodic f-plane of section 4.2
 (the planar shallow-water system, no metric terms).
 
+``advection`` is the same discretisation of planar linear advection (section
+4.1's convergence test), pinned by the paper's printed errors.
+
 ``mlp`` is the oracle of the learned right-hand-side correction, an addition
 to the paper's method (a small network that corrects the r = 1 right-hand
 side towards the projection of higher-order runs); it is pinned by finite
@@ -24,8 +27,9 @@ polynomials and the paper's printed Butcher tableaux).
 from .basis import gauss_legendre, legendre
 from .sphere import SphereDG, project_order
 from .plane import PlaneDG
+from .advection import AdvectionDG
 from . import mlp
 from .timestep import ssp_rk3, butcher_step
 
-__all__ = ["gauss_legendre", "legendre", "SphereDG", "PlaneDG", "project_order", "ssp_rk3",
-           "butcher_step", "mlp"]
+__all__ = ["gauss_legendre", "legendre", "SphereDG", "PlaneDG", "AdvectionDG", "project_order",
+           "ssp_rk3", "butcher_step", "mlp"]
