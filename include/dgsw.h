@@ -317,6 +317,32 @@ int dg_rk_step_learned(dg_ctx *ctx, const dg_learned *net, void *q, void *work,
                        void *workspace, double dt, int32_t nsteps, int32_t *fallbacks,
                        void *hip_stream);
 
+/* ---- Planar linear advection (section 4.1's convergence test, equation
+ * "lin_adv"): du/dt + div(beta u) = 0 on the periodic rectangle [0, lx] x
+ * [0, ly], nx x ny elements, the same modal DG discretisation with the upwind
+ * (Rusanov) flux.  One variable: state u[E][N], e = j nx + i, m = b(r+1) + a. */
+typedef struct dg_adv dg_adv;
+typedef struct {
+  int32_t abi_version;  /* must be DG_ABI_VERSION                                     */
+  int32_t nx, ny;       /* elements along x and y, >= 1                               */
+  int32_t order;        /* polynomial degree r, 0..6                                  */
+  int32_t dtype;        /* DG_F64 or DG_F32                                           */
+  int32_t reserved;     /* must be 0                                                   */
+  double lx, ly;        /* domain lengths, > 0                                         */
+  double bx, by;        /* constant velocity beta, finite                              */
+} dg_adv_desc;
+/* Assembles the linear operator on the host (five (r+1)^2 x (r+1)^2 matrices:
+ * the element and its four neighbours) and uploads it; *out NULL on failure. */
+int dg_adv_init(const dg_adv_desc *desc, void *hip_stream, dg_adv **out);
+int dg_adv_free(dg_adv *adv);
+int dg_adv_state_size(const dg_adv *adv, int64_t *n_values);   /* E * N */
+/* dqdt = M^-1 h(q); q and dqdt must not overlap. */
+int dg_adv_rhs(dg_adv *adv, const void *q, void *dqdt, void *hip_stream);
+/* nsteps steps of a DG_SSP_RK* or DG_RK4 scheme, as dg_rk_step (work: 1, 2, 2
+ * or 3 states). */
+int dg_adv_rk_step(dg_adv *adv, void *q, void *work, double dt, int32_t scheme, int32_t nsteps,
+                   void *hip_stream);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char *dg_last_error(void);
 

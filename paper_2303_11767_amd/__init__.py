@@ -10,9 +10,9 @@ import math
 
 from ._lib import (DG_ABI_VERSION, DG_ALPHA_GLOBAL, DG_ALPHA_LOCAL, DG_F32, DG_F64,
                    DG_METRIC_BALANCED, DG_METRIC_POINTWISE, DG_SSP_RK1, DG_SSP_RK2, DG_SSP_RK3,
-                   DG_RK4, DGError, MeshDesc, PlaneDesc, check, load)
+                   DG_RK4, AdvDesc, DGError, MeshDesc, PlaneDesc, check, load)
 
-__all__ = ["Mesh", "Plane", "Ensemble", "Graph", "DGError", "cfl_time_step", "DG_SSP_RK1",
+__all__ = ["Mesh", "Plane", "Advection", "Ensemble", "Graph", "DGError", "cfl_time_step", "DG_SSP_RK1",
            "DG_SSP_RK2", "DG_SSP_RK3", "DG_RK4"]
 
 RADIUS, GRAVITY, OMEGA = 6.371e6, 9.80616, 7.292e-5
@@ -232,6 +232,71 @@ class Plane(Mesh):
         md.abi_version, md.n_lon, md.n_lat, md.order, md.dtype = DG_ABI_VERSION, d.nx, d.ny, d.order, d.dtype
         md.alpha_mode, md.alpha, md.radius, md.gravity, md.h_ref = d.alpha_mode, d.alpha, 1.0, d.gravity, d.h_ref
         self._setup(md, ctx, owns=True)
+
+
+class Advection:
+    """Planar linear advection du/dt + div(beta u) = 0 on the periodic
+    rectangle (section 4.1's test): a dg_adv of the C library; state u[E][N]."""
+
+    _WORK = {DG_SSP_RK1: 1, DG_SSP_RK2: 2, DG_SSP_RK3: 2, DG_RK4: 3}
+
+    def __init__(self, nx, ny, order, lx=1.0, ly=1.0, beta=(1.0, 1.0), dtype="f64", stream=None):
+        import torch
+        self._lib = load()
+        d = AdvDesc()
+        d.abi_version, d.nx, d.ny, d.order = DG_ABI_VERSION, int(nx), int(ny), int(order)
+        d.dtype = {"f64": DG_F64, "f32": DG_F32}[dtype]
+        d.reserved = 0
+        d.lx, d.ly, d.bx, d.by = float(lx), float(ly), float(beta[0]), float(beta[1])
+        h = ctypes.c_void_p()
+        check(self._lib.dg_adv_init(ctypes.byref(d), _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.desc = d
+        self.nx, self.ny, self.order = d.nx, d.ny, d.order
+        self.n = self.order + 1
+        self.N = self.n * self.n
+        self.E = self.nx * self.ny
+        self.shape = (self.E, self.N)
+        self.dtype = torch.float64 if dtype == "f64" else torch.float32
+        self.dx, self.dy = float(lx) / nx, float(ly) / ny
+
+    def _ptr(self, t, name, numel=None):
+        if not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous GPU tensor of {self.dtype}")
+        if t.numel() != (numel if numel is not None else self.E * self.N):
+            raise ValueError(f"{name} has {t.numel()} values")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty_state(self, device="cuda"):
+        import torch
+        return torch.empty(self.shape, dtype=self.dtype, device=device)
+
+    def empty_work(self, scheme=DG_RK4, device="cuda"):
+        import torch
+        return torch.empty(self._WORK[scheme] * self.E * self.N, dtype=self.dtype, device=device)
+
+    def rhs(self, q, out=None, stream=None):
+        if out is None:
+            out = self.empty_state(q.device)
+        check(self._lib.dg_adv_rhs(self._h, self._ptr(q, "q"), self._ptr(out, "out"), _stream_handle(stream)))
+        return out
+
+    def rk_step(self, q, work, dt, scheme=DG_RK4, nsteps=1, stream=None):
+        check(self._lib.dg_adv_rk_step(self._h, self._ptr(q, "q"),
+                                       self._ptr(work, "work", self._WORK[scheme] * self.E * self.N),
+                                       float(dt), int(scheme), int(nsteps), _stream_handle(stream)))
+        return q
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dg_adv_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 class Ensemble:
     """Independent meshes of different size and order advanced together: one

@@ -30,7 +30,8 @@ EXPORTS = ("dg_init_mesh", "dg_init_plane", "dg_set_kernel", "dg_get_kernel", "d
            "dg_ens_get_schedule", "dg_ens_autotune", "dg_graph_rk", "dg_graph_ens",
            "dg_graph_launch", "dg_graph_free", "dg_mlp_param_count", "dg_mlp_workspace_size",
            "dg_mlp_forward", "dg_mlp_train_step", "dg_project", "dg_features",
-           "dg_learned_workspace_size", "dg_rhs_learned", "dg_rk_step_learned")
+           "dg_learned_workspace_size", "dg_rhs_learned", "dg_rk_step_learned",
+           "dg_adv_init", "dg_adv_free", "dg_adv_state_size", "dg_adv_rhs", "dg_adv_rk_step")
 
 
 class Learned(ctypes.Structure):
@@ -61,6 +62,13 @@ class PlaneDesc(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("alpha_mode", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("lx", ctypes.c_double), ("ly", ctypes.c_double),
                 ("gravity", ctypes.c_double), ("f", ctypes.c_double), ("h_ref", ctypes.c_double)]
+
+
+class AdvDesc(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("bx", ctypes.c_double),
+                ("by", ctypes.c_double)]
 
 
 _lib = None
@@ -118,6 +126,11 @@ def load():
     lib.dg_rhs_learned.argtypes = [vp, ctypes.POINTER(Learned), vp, vp, vp, vp, vp]
     lib.dg_rk_step_learned.argtypes = [vp, ctypes.POINTER(Learned), vp, vp, vp, ctypes.c_double, i32,
                                        vp, vp]
+    lib.dg_adv_init.argtypes = [ctypes.POINTER(AdvDesc), vp, ctypes.POINTER(vp)]
+    lib.dg_adv_free.argtypes = [vp]
+    lib.dg_adv_state_size.argtypes = [vp, i64p]
+    lib.dg_adv_rhs.argtypes = [vp, vp, vp, vp]
+    lib.dg_adv_rk_step.argtypes = [vp, vp, vp, ctypes.c_double, i32, i32, vp]
     lib.dg_last_error.argtypes = []
     lib.dg_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:

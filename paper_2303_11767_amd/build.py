@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdgsw.so")
 SOURCES = ["dgsw_tables.cpp", "dgsw_kernels.hip", "dgsw_api.hip", "dgsw_ensemble.hip",
-           "dgsw_mlp.hip", "dgsw_learned.hip"]
+           "dgsw_mlp.hip", "dgsw_learned.hip", "dgsw_advection.hip"]
 ARCH = os.environ.get("DGSW_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -91,10 +91,28 @@ def test_plane_descriptor_validation(kw, code):
     assert len(lib.dg_last_error()) > 0
 
 
+@pytest.mark.parametrize("kw,code", [
+    ({"abi_version": 0}, -1), ({"nx": 0}, -1), ({"order": 7}, -6), ({"order": -1}, -1),
+    ({"dtype": 2}, -2), ({"reserved": 1}, -1), ({"lx": 0.0}, -1), ({"by": float("nan")}, -1),
+])
+def test_advection_descriptor_validation(kw, code):
+    lib = _lib.load()
+    d = _lib.AdvDesc()
+    d.abi_version, d.nx, d.ny, d.order, d.dtype, d.reserved = 1, 8, 8, 3, 0, 0
+    d.lx, d.ly, d.bx, d.by = 1.0, 1.0, 1.0, 1.0
+    for k, v in kw.items():
+        setattr(d, k, v)
+    h = ctypes.c_void_p(123)
+    assert lib.dg_adv_init(ctypes.byref(d), None, ctypes.byref(h)) == code
+    assert h.value is None
+
+
 def test_null_arguments():
     lib = _lib.load()
     assert lib.dg_init_mesh(None, None, None) == -1
     assert lib.dg_init_plane(None, None, None) == -1
+    assert lib.dg_adv_init(None, None, None) == -1
+    assert lib.dg_adv_free(None) == 0
     assert lib.dg_free(None) == 0
     n = ctypes.c_int64()
     assert lib.dg_state_size(None, ctypes.byref(n)) == -1
