@@ -298,6 +298,42 @@ def planar_section(dtype="f64"):
                               "(G4GT, Table of computational times, p = 3)"}}
 
 
+def advection_section():
+    """Section 4.1's convergence run on the GPU at the paper's finest mesh:
+    160 x 160 elements, r = 3, FP64, classical RK4 to T = 1; time, per-stage
+    bandwidth (13 state transfers per RK4 step) and the L2 error against the
+    exact solution beside the paper's printed 5.030e-10."""
+    import numpy as np
+    import torch
+
+    import paper_2303_11767_amd as dg
+    from dg_inputs import sine_square
+    k, p = 160, 3
+    adv = dg.Advection(k, k, p)
+    q0 = torch.from_numpy(sine_square(k, p)).cuda()
+    q = q0.clone()
+    work = adv.empty_work()
+    n = int(np.ceil(1.0 / (0.1 * (1.0 / k) / ((2 * p + 1) * 2.0))))
+    adv.rk_step(q, work, 1.0 / n, nsteps=10)
+    q.copy_(q0)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    adv.rk_step(q, work, 1.0 / n, nsteps=n)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) * 1e-3
+    state = q.numel() * q.element_size()
+    # after one period the exact solution is the initial field again; the
+    # error is measured against its projection (the paper's is against the
+    # exact field, which adds the projection error in quadrature)
+    err = float(torch.sqrt(((q - q0) ** 2).sum() * (1.0 / k) ** 2 / 4.0).item())
+    return {"workload": "linear advection, 160x160 periodic unit square, r=3, RK4 to T=1",
+            "steps": n, "seconds": sec, "us_per_stage": sec / (4 * n) * 1e6,
+            "alg_GBs": 13 * state * n / sec / 1e9, "l2_error_vs_projection": err,
+            "paper_l2_error": 5.030e-10}
+
+
 def profile_probe(args):
     """Short run for rocprofv3 counter passes: a few 3-stage cycles of the
     stage kernel, then device-to-device copies of a known size (the
@@ -358,6 +394,7 @@ def main():
     if not args.no_extras:
         out["ensemble"] = ensemble_section()
         out["planar"] = planar_section()
+        out["advection"] = advection_section()
         if os.path.exists(LEARNED_MODEL):
             out["learned"] = learned_section(LEARNED_MODEL)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)

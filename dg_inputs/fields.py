@@ -191,3 +191,16 @@ def random_plane_state(nx, ny, order, lx, ly, seed, h0=1000.0, dh=5.0, vel=2.0, 
     q = np.einsum("vjsip,s,p,pa,sb->jivba", f, w, w, Vx, Vx)
     return np.ascontiguousarray(q.reshape(ny * nx, 3, n * n))
 
+
+def sine_square(k, order):
+    """u0 = sin(2 pi x) sin(2 pi y) on the unit square with k x k elements
+    (section 4.1's initial condition), projected unweighted onto the
+    orthonormal basis; layout u[e][m], e = j k + i, m = b (r+1) + a."""
+    n = order + 1
+    x, w = npleg.leggauss(n + 6)
+    xs = (np.arange(k)[:, None] + 0.5 * (1.0 + x[None, :])) / k       # [i, p]
+    Vx = _orthonormal_vander(order, x)
+    s = np.sin(2 * np.pi * xs)                                          # [i, p]
+    c = np.einsum("ip,p,pa->ia", s, w, Vx)                              # 1-D coefficients
+    return np.ascontiguousarray(np.einsum("jb,ia->jiba", c, c).reshape(k * k, n * n))
+
