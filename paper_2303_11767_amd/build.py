@@ -14,8 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdgsw.so")
-SOURCES = ["dgsw_tables.cpp", "dgsw_kernels.hip", "dgsw_api.hip", "dgsw_ensemble.hip",
-           "dgsw_mlp.hip", "dgsw_learned.hip", "dgsw_advection.hip"]
+SOURCES = ["dgsw_tables.cpp", "dgsw_kernels.hip", "dgsw_ens_kernels.hip", "dgsw_api.hip",
+           "dgsw_ensemble.hip", "dgsw_mlp.hip", "dgsw_learned.hip", "dgsw_advection.hip"]
 ARCH = os.environ.get("DGSW_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -33,18 +33,23 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose=False):
+def build(verbose=False, jobs=None):
+    """Compile every source (in parallel, one hipcc per source) and link."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD, src + ".o")
         if src.endswith(".hip"):
-            cmd = [HIPCC] + COMMON + DEVICE + ["-c", path, "-o", obj]
+            cmds.append([HIPCC] + COMMON + DEVICE + ["-c", path, "-o", obj])
         else:
-            cmd = [HIPCC] + COMMON + ["-c", path, "-o", obj]
-        _run(cmd, verbose)
+            cmds.append([HIPCC] + COMMON + ["-c", path, "-o", obj])
         objs.append(obj)
+    jobs = jobs or min(len(cmds), max(1, os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "--offload-arch=" + ARCH, "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)
