@@ -11,7 +11,7 @@
 // element and its east, west, north and south neighbours); a stage is then
 // dq_e/dt = sum_k A_k q_{neighbour k of e}, a dense contraction of length 5N
 // per output mode.  Work unit: one (element, mode) per lane; the matrices
-// are staged in LDS per workgroup, the neighbour rows come through L1/L2.
+// and the workgroup's stencil rows are staged in LDS.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -102,36 +102,52 @@ struct AdvArgs {
   double c0, c1, ce, dt, ca, cb;
 };
 
-// One lane per (element, output mode); the five matrices in LDS.
+// One lane per (element, output mode), G = 256 / N consecutive elements per
+// workgroup.  The five matrices and the G elements' five stencil rows are
+// staged in LDS (the rows with coalesced loads, one value per lane per slot),
+// then every lane contracts its output row of each matrix with its element's
+// rows: 5N multiply-adds from LDS.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_adv_stage(const T *__restrict__ ops, const T *__restrict__ q,
                                                    const T *q0, const T *qa, const T *qb, T *out, int nx, int ny,
                                                    int combine, T c0, T c1, T ce, T dt, T ca, T cb) {
-  __shared__ T sA[kSlots * N * N];
-  for (int k = threadIdx.x; k < kSlots * N * N; k += 256) sA[k] = ops[k];
-  __syncthreads();
-  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  constexpr int G = 256 / N;
+  // padded strides: rows of different output modes / elements start in
+  // different LDS banks
+  constexpr int LA = N + 1, LQ = kSlots * N + 1;
+  __shared__ T sA[kSlots * N * LA];
+  __shared__ T sQ[G * LQ];
+  for (int k = threadIdx.x; k < kSlots * N * N; k += 256) sA[(k / N) * LA + k % N] = ops[k];
   const int64_t E = (int64_t)nx * ny;
-  if (gid >= E * N) return;
-  const int e = (int)(gid / N), m = (int)(gid - (int64_t)e * N);
+  const int g = threadIdx.x / N, m = threadIdx.x - g * N;
+  const int64_t e64 = (int64_t)blockIdx.x * G + g;
+  const bool live = g < G && e64 < E;
+  const int e = live ? (int)e64 : 0;
   const int j = e / nx, i = e - j * nx;
-  const int nb[kSlots] = {e, j * nx + (i + 1 == nx ? 0 : i + 1), j * nx + (i == 0 ? nx - 1 : i - 1),
-                          (j + 1 == ny ? 0 : j + 1) * nx + i, (j == 0 ? ny - 1 : j - 1) * nx + i};
+  if (g < G) {
+    const int nb[kSlots] = {e, j * nx + (i + 1 == nx ? 0 : i + 1), j * nx + (i == 0 ? nx - 1 : i - 1),
+                            (j + 1 == ny ? 0 : j + 1) * nx + i, (j == 0 ? ny - 1 : j - 1) * nx + i};
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) sQ[g * LQ + k * N + m] = q[(size_t)nb[k] * N + m];
+  }
+  __syncthreads();
+  if (!live) return;
   T acc = T(0);
 #pragma unroll
   for (int k = 0; k < kSlots; ++k) {
-    const T *row = sA + (k * N + m) * N;
-    const T *src = q + (size_t)nb[k] * N;
+    const T *row = sA + (k * N + m) * LA;
+    const T *src = sQ + g * LQ + k * N;
 #pragma unroll
     for (int n = 0; n < N; ++n) acc += row[n] * src[n];
   }
   const size_t o = (size_t)e * N + m;
+  const T qo = sQ[g * LQ + m];
   T res;
   if (combine == 2) {
     const T b0 = q0[o];
-    res = b0 + dt * acc + (c1 * (q[o] - b0) + ((qa ? ca * (qa[o] - b0) : T(0)) + (qb ? cb * (qb[o] - b0) : T(0))));
+    res = b0 + dt * acc + (c1 * (qo - b0) + ((qa ? ca * (qa[o] - b0) : T(0)) + (qb ? cb * (qb[o] - b0) : T(0))));
   } else if (combine == 1) {
-    const T y = q[o] + dt * acc;
+    const T y = qo + dt * acc;
     res = y + c0 * ((c0 != T(0) ? q0[o] : T(0)) - y) + ce * y;
   } else {
     res = acc;
@@ -141,8 +157,9 @@ __global__ __launch_bounds__(256) void k_adv_stage(const T *__restrict__ ops, co
 
 template <typename T, int N>
 hipError_t launch_adv_t(const dg_adv *a, const AdvArgs &g, hipStream_t s) {
-  const int64_t total = (int64_t)g.nx * g.ny * N;
-  const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+  constexpr int G = 256 / N;
+  const int64_t E = (int64_t)g.nx * g.ny;
+  const dim3 grid((unsigned)((E + G - 1) / G)), block(256);
   hipLaunchKernelGGL((k_adv_stage<T, N>), grid, block, 0, s, static_cast<const T *>(a->d_ops),
                      static_cast<const T *>(g.q), static_cast<const T *>(g.q0), static_cast<const T *>(g.qa),
                      static_cast<const T *>(g.qb), static_cast<T *>(g.out), g.nx, g.ny, g.combine, T(g.c0), T(g.c1),
