@@ -137,11 +137,25 @@ enum { DG_KERNEL_LINE = 0, DG_KERNEL_HALF = 1 };
 int dg_set_kernel(dg_ctx *ctx, int32_t kernel);
 int dg_get_kernel(const dg_ctx *ctx, int32_t *kernel);
 
+/* Identical vertical layers (section 5.2.2: decoupled two-dimensional problems
+ * stacked in the vertical and solved side by side).  After this call every
+ * state-shaped buffer of the context (q, dqdt, q0, out, the work buffers and
+ * the forcing) holds n_levels independent copies of the mesh state back to
+ * back, [n_levels][E][3][N]; dg_state_size and dg_work_size scale with it;
+ * dg_rhs, dg_rk_step, dg_rk_stage and dg_graph_rk advance all layers with one
+ * launch per stage; dg_mass returns the integrals summed over the layers.
+ * Default 1.  1 <= n_levels <= 65535 and fewer than 2^31 wavefronts over all
+ * layers, else DG_EINVAL.  Contexts owned by an ensemble (dg_ens_member) and
+ * the learned calls (dg_rhs_learned, dg_rk_step_learned, dg_project,
+ * dg_features) accept one layer only (DG_EUNSUPPORTED). */
+int dg_set_levels(dg_ctx *ctx, int32_t n_levels);
+int dg_get_levels(const dg_ctx *ctx, int32_t *n_levels);
+
 /* Release a context and its device tables.  NULL is accepted.  The caller
  * must make sure no enqueued work still uses the context. */
 int dg_free(dg_ctx *ctx);
 
-/* Number of scalars in one state buffer: E * 3 * N. */
+/* Number of scalars in one state buffer: n_levels * E * 3 * N. */
 int dg_state_size(const dg_ctx *ctx, int64_t *n_values);
 
 /* Number of scalars the `work` argument of dg_rk_step must hold for the

@@ -117,6 +117,19 @@ class Mesh:
     def kernel(self, name):
         check(self._lib.dg_set_kernel(self._ctx, {"line": 0, "half": 1}[name]))
 
+    # -- identical vertical layers (dg_set_levels)
+    @property
+    def levels(self):
+        """Independent copies of the mesh state held by every state buffer."""
+        k = ctypes.c_int32()
+        check(self._lib.dg_get_levels(self._ctx, ctypes.byref(k)))
+        return k.value
+
+    @levels.setter
+    def levels(self, n):
+        check(self._lib.dg_set_levels(self._ctx, int(n)))
+        self.shape = (self.E, 3, self.N) if int(n) == 1 else (int(n), self.E, 3, self.N)
+
     # -- sizes
     def state_size(self):
         n = ctypes.c_int64()

@@ -105,6 +105,8 @@ int make_ctx(const dg_mesh_desc *desc, const dgsw::HostTables &t, hipStream_t s,
   c->N = c->np * c->np;
   c->E = desc->n_lon * desc->n_lat;
   c->state_n = (int64_t)c->E * 3 * c->N;
+  c->level_n = c->state_n;
+  c->levels = 1;
   c->elem_bytes = desc->dtype == DG_F64 ? 8 : 4;
   {
     double cmin = 1.0;
@@ -227,6 +229,25 @@ int dg_get_kernel(const dg_ctx *ctx, int32_t *kernel) {
   return DG_OK;
 }
 
+int dg_set_levels(dg_ctx *ctx, int32_t n_levels) {
+  if (!ctx) return fail(DG_EINVAL, "ctx is NULL");
+  if (n_levels < 1 || n_levels > 65535) return fail(DG_EINVAL, "n_levels must be in 1..65535");
+  if (ctx->member && n_levels != 1)
+    return fail(DG_EUNSUPPORTED, "an ensemble member holds one layer");
+  // wavefronts of one layer in the denser (half-line) layout
+  const int64_t per = (int64_t)dgsw::waves_per_row(ctx->np, ctx->d.n_lon) * 2 * ctx->d.n_lat;
+  if (per * n_levels >= ((int64_t)1 << 31)) return fail(DG_EINVAL, "too many layers for one launch");
+  ctx->levels = n_levels;
+  ctx->state_n = ctx->level_n * n_levels;
+  return DG_OK;
+}
+
+int dg_get_levels(const dg_ctx *ctx, int32_t *n_levels) {
+  if (!ctx || !n_levels) return fail(DG_EINVAL, "NULL argument");
+  *n_levels = ctx->levels;
+  return DG_OK;
+}
+
 int dg_free(dg_ctx *ctx) {
   release(ctx);
   return DG_OK;
@@ -277,6 +298,7 @@ static int stage(dg_ctx *c, const void *q, const void *q0, void *out, int combin
   a.alpha_global = c->d.alpha_mode == DG_ALPHA_GLOBAL;
   a.periodic_y = c->periodic_y;
   a.variant = c->kernel;
+  a.levels = c->levels;
   a.combine = combine;
   a.c0 = c0;
   a.c1 = c1;
@@ -305,6 +327,7 @@ static int stage_general(dg_ctx *c, const void *q, const void *q0, void *out, do
   a.alpha_global = c->d.alpha_mode == DG_ALPHA_GLOBAL;
   a.periodic_y = c->periodic_y;
   a.variant = c->kernel;
+  a.levels = c->levels;
   a.combine = 2;
   a.c0 = 1.0 - c1 - ca - cb;
   a.c1 = c1;
@@ -408,7 +431,8 @@ int dg_mass(dg_ctx *ctx, const void *q, double out[3], void *hip_stream) {
   if (!aligned16(q)) return fail(DG_EINVAL, "q must be 16-byte aligned");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   hipError_t e = dgsw::launch_mass(ctx->d.dtype == DG_F64 ? 0 : 1, ctx->np, q, ctx->d_mass_w,
-                                   ctx->d.n_lon, ctx->E, ctx->d_partial, ctx->d_out4, s);
+                                   ctx->d.n_lon, ctx->E, ctx->levels, ctx->d_partial,
+                                   ctx->d_out4, s);
   if (e != hipSuccess) return hip_fail(e, "mass kernel launch");
   double h4[4];
   if ((e = hipMemcpyAsync(h4, ctx->d_out4, sizeof(h4), hipMemcpyDeviceToHost, s)) != hipSuccess)

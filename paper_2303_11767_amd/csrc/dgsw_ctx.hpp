@@ -24,6 +24,9 @@ struct dg_ctx {
   double mass_area = 0.0;      // sum over elements of mass_w[j][0]
   int periodic_y = 0;          // 1: the doubly periodic plane
   int kernel = 0;              // DG_KERNEL_LINE or DG_KERNEL_HALF
+  int levels = 1;              // identical layers held by every state buffer
+  int64_t level_n = 0;         // values of one layer, E * 3 * N
+  int member = 0;              // 1: owned by an ensemble (one layer only)
 };
 
 namespace dgsw {

@@ -58,6 +58,7 @@ struct StageLaunch {
   double c0, c1, dt;
   const void *qa = nullptr, *qb = nullptr;   // extra operands of combine == 2
   double ca = 0.0, cb = 0.0;
+  int levels = 1;       // identical layers, each E * 3 * N values after the previous one
 };
 
 // dtype 0 = double, 1 = float; np = order + 1.  Returns a hipError_t.
@@ -103,10 +104,11 @@ void fill_glob(int dtype, int np, const HostTables &t, double g, double radius,
 void fill_rows(int dtype, int np, const HostTables &t, void *dst);
 
 // Mass diagnostic: partial sums per block, then one ordered final sum.
-// out4 (device) = (mass_h, mass_hu, mass_hv, count of non-finite values).
+// out4 (device) = (mass_h, mass_hu, mass_hv, count of non-finite values),
+// summed over the layers.
 int mass_blocks();
 hipError_t launch_mass(int dtype, int np, const void *q, const double *mass_w,
-                       int n_lon, int E, double *partial, double *out4,
+                       int n_lon, int E, int levels, double *partial, double *out4,
                        hipStream_t s);
 
 }  // namespace dgsw

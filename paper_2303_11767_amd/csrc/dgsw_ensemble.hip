@@ -182,6 +182,7 @@ int dg_ens_init(const dg_mesh_desc *members, int32_t n_members, void *hip_stream
       ens_release(e);
       return rc;
     }
+    c->member = 1;
     e->members.push_back(c);
     e->npmax = std::max(e->npmax, c->np);
     e->off[m + 1] = e->off[m] + (c->state_n + align - 1) / align * align;

@@ -4,16 +4,36 @@
 
 namespace dgsw {
 
-template <typename T, int NP, int WPB, int CM>
-__global__ __launch_bounds__(64 * WPB) void k_dg_stage_h2(StageArgs<T, NP> A, int segs) {
+// PK: wavefront w of a layer takes the GPW consecutive elements from w GPW on,
+// across row ends (needs GPW <= n_lon; ceil(E / GPW) wavefronts); otherwise
+// row-aligned segments, segs per row.  At least two wavefronts per SIMD: the
+// register budget stays within 256 (the FP64 r >= 5 cases sit at that edge,
+// where a few spilled values cost far less than half the occupancy).
+template <typename T, int NP, int WPB, int CM, bool PK>
+__global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * WPB) void k_dg_stage_h2(
+    StageArgs<T, NP> A, int segs) {
   using S_ = ShapeH2<T, NP>;
   __shared__ T tab_all[WPB][S_::TB];
   __shared__ T sh_all[WPB][S_::SLOTS * S_::SH];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int blk = xcd_block(blockIdx.x, gridDim.x) * WPB + wv;
-  if (blk >= segs * A.n_lat) return;
-  const int j = blk / segs;
-  stage_wave_h2<T, NP, CM>(A, j, blk - j * segs, threadIdx.x & 63, tab_all[wv], sh_all[wv]);
+  int blk = xcd_block(blockIdx.x, gridDim.x) * WPB + wv;
+  const int E = A.n_lon * A.n_lat;
+  const int per = PK ? (E + S_::GPW - 1) / S_::GPW : segs * A.n_lat;   // wavefronts of one layer
+  if (blk >= per * A.levels) return;
+  const int lev = blk / per;
+  blk -= lev * per;
+  int j0, e0, e_end;
+  if (PK) {
+    e0 = blk * S_::GPW;
+    j0 = e0 / A.n_lon;
+    e_end = E;
+  } else {
+    j0 = blk / segs;
+    e0 = j0 * A.n_lon + (blk - j0 * segs) * S_::GPW;
+    e_end = (j0 + 1) * A.n_lon;
+  }
+  stage_wave_h2<T, NP, CM, PK>(layer_args(A, lev), j0, e0, e_end, threadIdx.x & 63, tab_all[wv],
+                               sh_all[wv]);
 }
 
 template <typename T, int NP, int WPB, int CM>
@@ -25,10 +45,14 @@ __global__ __launch_bounds__(64 * WPB) void k_dg_stage(StageArgs<T, NP> A, int s
   __shared__ T tab_all[WPB][S_::TB];
   __shared__ T sh_all[WPB][(S_::GPW + 1) * S_::SH];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int blk = xcd_block(blockIdx.x, gridDim.x) * WPB + wv;
-  if (blk >= segs * A.n_lat) return;      // spare wavefront of the last workgroup
+  int blk = xcd_block(blockIdx.x, gridDim.x) * WPB + wv;
+  const int per = segs * A.n_lat;            // wavefronts of one layer
+  if (blk >= per * A.levels) return;         // spare wavefront of the last workgroup
+  const int lev = blk / per;
+  blk -= lev * per;
   const int j = blk / segs;
-  stage_wave<T, NP, CM>(A, j, blk - j * segs, threadIdx.x & 63, tab_all[wv], sh_all[wv]);
+  stage_wave<T, NP, CM>(layer_args(A, lev), j, blk - j * segs, threadIdx.x & 63, tab_all[wv],
+                        sh_all[wv]);
 }
 
 // ------------------------------------------------------------------ mass
@@ -61,13 +85,15 @@ __device__ __forceinline__ void block_sum4(double v[4], double *sh) {
 template <typename T, int NP>
 __global__ __launch_bounds__(kMassThreads) void k_mass_partial(const T *__restrict__ q,
                                                                const double *__restrict__ mw,
-                                                               int n_lon, int E,
+                                                               int n_lon, int E, long long E_all,
                                                                double *__restrict__ partial) {
   constexpr int N = NP * NP;
   __shared__ double sh[4 * kMassThreads];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int e = blockIdx.x * kMassThreads + threadIdx.x; e < E; e += gridDim.x * kMassThreads) {
-    const int j = e / n_lon;
+  // E_all = layers x E elements; the row of element e of any layer
+  for (long long e = blockIdx.x * kMassThreads + threadIdx.x; e < E_all;
+       e += (long long)gridDim.x * kMassThreads) {
+    const int j = (int)(e % E) / n_lon;
     const T *qe = q + (size_t)e * 3 * N;
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
@@ -116,6 +142,8 @@ static StageArgs<T, NP> stage_args(const StageLaunch &a) {
   A.c1 = T(a.c1);
   A.ce = T(a.c0 + a.c1 - 1.0);
   A.dt = T(a.dt);
+  A.levels = a.levels;
+  A.lstride = (long long)a.E * 3 * NP * NP;
   return A;
 }
 
@@ -125,30 +153,37 @@ static hipError_t launch_stage_t(const StageLaunch &a, hipStream_t s) {
   if (a.variant == 1) {
     constexpr int GPW = ShapeH2<T, NP>::GPW;
     const int segs = (a.n_lon + GPW - 1) / GPW;
-    const int waves = segs * a.n_lat;
+    // rows that end in a partly filled wavefront: pack the elements across
+    // row ends instead (a wavefront then spans at most two rows)
+    const bool packed = GPW <= a.n_lon && a.n_lon % GPW != 0;
+    const int per = packed ? (a.n_lon * a.n_lat + GPW - 1) / GPW : segs * a.n_lat;
+    const int waves = per * a.levels;
     const bool big = waves >= 4096;
     const dim3 grid(big ? (waves + 3) / 4 : waves), block(big ? 256 : 64);
+#define DGSW_H2(WPB_, CM_)                                                                   \
+  do {                                                                                       \
+    if (packed) hipLaunchKernelGGL((k_dg_stage_h2<T, NP, WPB_, CM_, true>), grid, block, 0, s, A, segs); \
+    else hipLaunchKernelGGL((k_dg_stage_h2<T, NP, WPB_, CM_, false>), grid, block, 0, s, A, segs);      \
+  } while (0)
     switch (a.combine) {
       case 0:
-        if (big) hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 4, 0>), grid, block, 0, s, A, segs);
-        else hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 1, 0>), grid, block, 0, s, A, segs);
+        if (big) DGSW_H2(4, 0); else DGSW_H2(1, 0);
         break;
       case 1:
-        if (big) hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 4, 1>), grid, block, 0, s, A, segs);
-        else hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 1, 1>), grid, block, 0, s, A, segs);
+        if (big) DGSW_H2(4, 1); else DGSW_H2(1, 1);
         break;
       case 2:
-        if (big) hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 4, 2>), grid, block, 0, s, A, segs);
-        else hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 1, 2>), grid, block, 0, s, A, segs);
+        if (big) DGSW_H2(4, 2); else DGSW_H2(1, 2);
         break;
       default:
         return hipErrorInvalidValue;
     }
+#undef DGSW_H2
     return hipGetLastError();
   }
   constexpr int GPW = Shape<T, NP>::GPW;
   const int segs = (a.n_lon + GPW - 1) / GPW;
-  const int waves = segs * a.n_lat;
+  const int waves = segs * a.n_lat * a.levels;
   const bool big = waves >= 4096;
   const dim3 grid(big ? (waves + 3) / 4 : waves), block(big ? 256 : 64);
   switch (a.combine) {
@@ -171,10 +206,10 @@ static hipError_t launch_stage_t(const StageLaunch &a, hipStream_t s) {
 }
 
 template <typename T, int NP>
-static hipError_t launch_mass_t(const void *q, const double *mw, int n_lon, int E,
+static hipError_t launch_mass_t(const void *q, const double *mw, int n_lon, int E, int levels,
                                 double *partial, double *out4, hipStream_t s) {
   hipLaunchKernelGGL((k_mass_partial<T, NP>), dim3(kMassBlocks), dim3(kMassThreads), 0, s,
-                     static_cast<const T *>(q), mw, n_lon, E, partial);
+                     static_cast<const T *>(q), mw, n_lon, E, (long long)E * levels, partial);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(kMassThreads), 0, s, partial, kMassBlocks, out4);
@@ -187,8 +222,8 @@ hipError_t launch_stage(int dtype, int np, const StageLaunch &a, hipStream_t s) 
 }
 
 hipError_t launch_mass(int dtype, int np, const void *q, const double *mw, int n_lon, int E,
-                       double *partial, double *out4, hipStream_t s) {
-  DGSW_DISPATCH(dtype, np, launch_mass_t, q, mw, n_lon, E, partial, out4, s)
+                       int levels, double *partial, double *out4, hipStream_t s) {
+  DGSW_DISPATCH(dtype, np, launch_mass_t, q, mw, n_lon, E, levels, partial, out4, s)
   return hipErrorInvalidValue;
 }
 

@@ -247,6 +247,7 @@ int dg_project(const dg_ctx *src, const dg_ctx *dst, const void *q_src, void *q_
   int rc = check_ptrs({src, dst, q_src, q_dst});
   if (rc != DG_OK) return rc;
   if (dst->np != 2) return fail(DG_EUNSUPPORTED, "projection target must be order 1");
+  if (src->levels != 1 || dst->levels != 1) return fail(DG_EUNSUPPORTED, "projection takes one layer");
   if (src->d.n_lon != dst->d.n_lon || src->d.n_lat != dst->d.n_lat || src->d.dtype != dst->d.dtype)
     return fail(DG_EINVAL, "source and target must share the mesh and dtype");
   hipError_t e = dgsw::launch_project1(src->d.dtype == DG_F64 ? 0 : 1, q_src, src->d.n_lon, src->E, src->np,
@@ -260,6 +261,7 @@ int dg_features(const dg_ctx *ctx, const void *q, const float *feat_mean, const 
   int rc = check_ptrs({ctx, q, X});
   if (rc != DG_OK) return rc;
   if (ctx->np != 2) return fail(DG_EUNSUPPORTED, "features are defined for order 1");
+  if (ctx->levels != 1) return fail(DG_EUNSUPPORTED, "features take one layer");
   if ((feat_mean == nullptr) != (feat_istd == nullptr)) return fail(DG_EINVAL, "give both mean and istd, or neither");
   hipError_t e = dgsw::launch_features_f32(ctx->d.dtype == DG_F64 ? 0 : 1, q, ctx->d.n_lon, ctx->d.n_lat, feat_mean,
                                            feat_istd, X, static_cast<hipStream_t>(hip_stream));
@@ -312,6 +314,7 @@ int check_learned(const dg_ctx *ctx, const dg_learned *net, const void *workspac
   if (!ctx || !net || !workspace) return fail(DG_EINVAL, "NULL argument");
   if (ctx->np != 2) return fail(DG_EUNSUPPORTED, "the learned correction is defined for order 1");
   if (ctx->periodic_y) return fail(DG_EUNSUPPORTED, "the learned correction is defined on the sphere");
+  if (ctx->levels != 1) return fail(DG_EUNSUPPORTED, "the learned correction takes one layer");
   if (!net->params || !net->feat_mean || !net->feat_istd || !net->out_mean || !net->out_std)
     return fail(DG_EINVAL, "dg_learned has a NULL table");
   if (!(net->kappa >= 0.0)) return fail(DG_EINVAL, "kappa must be >= 0");

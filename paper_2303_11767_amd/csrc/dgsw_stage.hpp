@@ -199,7 +199,23 @@ struct StageArgs {
   int n_lon, n_lat, alpha_global, combine, periodic_y;
   T c0, c1, dt, ca, cb;
   T ce;                  // c0 + c1 - 1, formed in FP64 on the host (0 for the schemes here)
+  int levels;            // identical layers, one after the other in every state buffer
+  long long lstride;     // values of one layer (E * 3 * N)
 };
+
+// The arguments of layer `lev`: every state-shaped pointer moved to the layer.
+template <typename T, int NP>
+__device__ __forceinline__ StageArgs<T, NP> layer_args(const StageArgs<T, NP> &A, int lev) {
+  StageArgs<T, NP> B = A;
+  const long long off = (long long)lev * A.lstride;
+  B.q = A.q + off;
+  B.q0 = A.q0 ? A.q0 + off : nullptr;
+  B.out = A.out + off;
+  B.forcing = A.forcing ? A.forcing + off : nullptr;
+  B.qa = A.qa ? A.qa + off : nullptr;
+  B.qb = A.qb ? A.qb + off : nullptr;
+  return B;
+}
 
 // One wavefront's share of a stage: GPW elements of one latitude row
 // (segment `seg` of row j), so the row's tables are wave-uniform (scalar
@@ -509,13 +525,16 @@ struct ShapeH2 {
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
   static constexpr int SH = cmax(NB + 12 * NP, 6 * NP * NP + 6 * NP);
   static constexpr int SLOTS = GPW + (SPARE ? 1 : 0);
-  // LDS copy of the tables: the GlobTab prefix (B, D, Pp, Pm, w) then the
-  // RowTab prefix (cosn, fc, snR, stR, BM, DM, MN, MS)
+  // LDS copy of the tables: the GlobTab prefix (B, D, Pp, Pm, w), then the
+  // whole RowTab of the wavefront's first row and of the row after it (a
+  // wavefront of consecutive elements may end in the next row)
   static constexpr int oB = 0, oD = N, oPp = 2 * N, oPm = 2 * N + NP, oW = 2 * N + 2 * NP;
   static constexpr int G1 = 2 * N + 3 * NP;
-  static constexpr int oCos = G1, oFc = G1 + NP, oSnR = G1 + 2 * NP, oStR = G1 + 3 * NP;
-  static constexpr int oBM = G1 + 4 * NP, oDM = oBM + N, oMN = oDM + N, oMS = oMN + NP;
-  static constexpr int TB = oMS + NP;
+  static constexpr int rCos = 0, rFc = NP, rSnR = 2 * NP, rStR = 3 * NP;
+  static constexpr int rBM = 4 * NP, rDM = rBM + N, rMN = rDM + N, rMS = rMN + NP;
+  static constexpr int rTop = rMS + NP, rBot = rTop + 1;
+  static constexpr int RP = rBot + 1;                   // values of one RowTab
+  static constexpr int TB = G1 + 2 * RP;
   static constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
   static constexpr int ROWALIGN = gcd(16, NP * (int)sizeof(T));
   // alignment of a half row starting at h K0 (even NP only; odd NP: element)
@@ -554,20 +573,25 @@ __device__ __forceinline__ void store_half(T *row, int h, const T (&r)[ShapeH2<T
   }
 }
 
-template <typename T, int NP, int CM>
-__device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const int j, const int seg,
-                                              const int lane, T *tab, T *sh) {
+// The wavefront takes the GPW consecutive elements e0 .. e0 + GPW - 1 below
+// e_end (lanes past it idle), starting in row j0.  PK = false: a row-aligned
+// segment (e_end = the end of row j0); PK = true: elements packed across
+// row ends (e_end = E, needs GPW <= n_lon), so the last ones may lie in row
+// j0 + 1 and each lane picks its row's tables.
+template <typename T, int NP, int CM, bool PK>
+__device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const int j0, const int e0,
+                                              const int e_end, const int lane, T *tab, T *sh) {
   using S_ = ShapeH2<T, NP>;
   constexpr int N = S_::N, GPW = S_::GPW, SH = S_::SH, NB = S_::NB, K0 = S_::K0;
   static_assert(sizeof(GlobTab<T, NP>) >= sizeof(T) * S_::G1, "GlobTab prefix");
   using RT_ = RowTab<T, NP>;
-  static_assert(offsetof(RT_, MS) == sizeof(T) * (S_::oMS - S_::G1), "RowTab prefix");
+  static_assert(offsetof(RT_, MS) == sizeof(T) * S_::rMS, "RowTab layout");
+  static_assert(sizeof(RT_) == sizeof(T) * S_::RP, "RowTab layout");
   const T *__restrict__ q = A.q;
   const T *q0 = A.q0;
   T *out = A.out;
   const T *__restrict__ forcing = A.forcing;
   const GlobTab<T, NP> *__restrict__ gt = A.gt;
-  const RowTab<T, NP> *__restrict__ rt = A.rows + j;
   const int n_lon = A.n_lon, n_lat = A.n_lat;
   const int combine = CM == CM_RUNTIME ? (A.combine != 0 ? 1 : 0) : CM;
   const T c0 = A.c0, c1 = A.c1, dt = A.dt;
@@ -576,10 +600,13 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
   if (idle) { g = GPW; r = lane - GPW * 2 * NP; }
   const int h = r >= NP ? 1 : 0;
   const int t = r - h * NP;
-  const int i_raw = seg * GPW + g;
-  const bool active = !idle && i_raw < n_lon;
-  const int i = i_raw < n_lon ? i_raw : n_lon - 1;
-  const int e = j * n_lon + i;
+  const int e_raw = e0 + g;
+  const bool active = !idle && e_raw < e_end;
+  const int e = e_raw < e_end ? e_raw : e_end - 1;      // tail lanes work on a valid element
+  const int rsel = PK && e >= (j0 + 1) * n_lon ? 1 : 0;  // 1: the element is in row j0 + 1
+  const int j = j0 + rsel;
+  const int i = e - j * n_lon;
+  const int ro = S_::G1 + rsel * S_::RP;                 // this lane's row tables in LDS
   T *S = sh + g * SH;
   const bool periodic = A.periodic_y != 0;
   const bool hasN = periodic || j < n_lat - 1, hasS = periodic || j > 0;
@@ -616,8 +643,11 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
       for (int k = 0; k < NP; ++k) xY[v][k] = T(0);
   }
   {
-    const T *g0 = &gt->B[0][0], *r0 = &rt->cosn[0];
-    for (int k = lane; k < S_::TB; k += 64) tab[k] = k < S_::G1 ? g0[k] : r0[k - S_::G1];
+    const T *g0 = &gt->B[0][0], *ra = &A.rows[j0].cosn[0];
+    const T *rb = &A.rows[j0 + 1 < n_lat ? j0 + 1 : j0].cosn[0];
+    constexpr int TBU = PK ? S_::TB : S_::G1 + S_::RP;     // the second row only when packed
+    for (int k = lane; k < TBU; k += 64)
+      tab[k] = k < S_::G1 ? g0[k] : (k < S_::G1 + S_::RP ? ra[k - S_::G1] : rb[k - S_::G1 - S_::RP]);
   }
   // per-lane coefficients: rows h K0 + k of B (clamped), this half's own edge
   // (h = 0: +1, h = 1: -1) and the facing edge of its neighbours
@@ -710,7 +740,7 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
     for (int v = 0; v < 3; ++v) { qm[v] = h ? nbY[v] : trY[v]; qp[v] = h ? trY[v] : nbY[v]; }
     rusanov_theta<T>(qm, qp, H, grav, fixed, alpha, GhY);
   }
-  const T fY = (h ? rt->cbot : rt->ctop) * invR;     // 0 at a pole edge
+  const T fY = tab[ro + (h ? S_::rBot : S_::rTop)] * invR;     // 0 at a pole edge
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
     FhX[v] *= invR;
@@ -738,16 +768,16 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
     const T rh = dg_rcp(hh);
     const T u = hu * rh, vv = hv * rh;
     const T pr = T(0.5) * grav * dh * (hh + H);
-    const T c = tab[S_::oCos + s];
+    const T c = tab[ro + S_::rCos + s];
     const T F0 = hu * invR, F1 = (hu * u + pr) * invR, F2 = hu * vv * invR;
     const T cR = c * invR;
     const T G0 = hv * cR, G1 = hv * u * cR, G2 = (hv * vv + pr) * cR;
-    const T C = tab[S_::oFc + s] + u * tab[S_::oSnR + s];
-    const T S1 = C * hv, S2 = -pr * tab[S_::oStR + s] - C * hu;
+    const T C = tab[ro + S_::rFc + s] + u * tab[ro + S_::rSnR + s];
+    const T S1 = C * hv, S2 = -pr * tab[ro + S_::rStR + s] - C * hu;
     const T m = valid ? T(1) : T(0);
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
-      const T bm = m * tab[S_::oBM + s * NP + b], dm = m * tab[S_::oDM + s * NP + b];
+      const T bm = m * tab[ro + S_::rBM + s * NP + b], dm = m * tab[ro + S_::rDM + s * NP + b];
       ZD[0][b] += F0 * bm; ZD[1][b] += F1 * bm; ZD[2][b] += F2 * bm;
       ZG[0][b] += G0 * dm; ZG[1][b] += G1 * dm; ZG[2][b] += G2 * dm;
       ZS[0][b] += S1 * bm; ZS[1][b] += S2 * bm;
@@ -760,7 +790,7 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
   for (int v = 0; v < 3; ++v)
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
-      const T my = tab[S_::oMN + h * NP + b];
+      const T my = tab[ro + S_::rMN + h * NP + b];
       const T zg = ZG[v][b] + (h ? GhY[v] : -GhY[v]) * my;
       const T zs = v == 0 ? T(0) : ZS[v - 1][b];
       PV[v][b] = cF * wt * ZD[v][b];
@@ -804,7 +834,7 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
   // ---- xi pass back to modes: lane t = latitude degree b, this half's a
   T bmt[NP], DA[NP][K0], BA[NP][K0], PpA[K0], PmA[K0];
 #pragma unroll
-  for (int p = 0; p < NP; ++p) bmt[p] = tab[S_::oBM + p * NP + t];       // BM[p][t]
+  for (int p = 0; p < NP; ++p) bmt[p] = tab[ro + S_::rBM + p * NP + t];   // BM[p][t]
 #pragma unroll
   for (int k = 0; k < K0; ++k) {
     const int a_raw = h * K0 + k;
