@@ -340,6 +340,58 @@ def advection_section():
             "paper_l2_error": 5.030e-10}
 
 
+def _plane_rk4_seconds(mesh, q, steps):
+    """Seconds per classical RK4 step over `steps` steps of dt = 100 s."""
+    import torch
+
+    import paper_2303_11767_amd as dg
+    work = mesh.empty_work(dg.DG_RK4)
+    mesh.rk_step(q, work, 100.0, scheme=dg.DG_RK4, nsteps=3)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    mesh.rk_step(q, work, 100.0, scheme=dg.DG_RK4, nsteps=steps)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) * 1e-3 / steps
+
+
+def scaling_section():
+    """The two scaling studies of section 5.2 with the section 4.2 f-plane
+    (r = 3, FP64, classical RK4, dt = 100 s, Gaussian bump):
+    horizontal, K x K elements for K = 20 .. 640 (the paper doubles K up to
+    640); vertical, 300 x 300 elements with nz identical layers advanced by
+    one launch per stage (dg_set_levels).  The paper reports these as
+    figures only; the numbers here are throughput per layer."""
+    import torch
+
+    import paper_2303_11767_amd as dg
+    from dg_inputs import gaussian_bump_plane
+    L = 1.0e7
+    horiz = []
+    for k in (20, 40, 80, 160, 320, 640):
+        mesh = dg.Plane(k, k, 3, L, L, f=1.0e-4, gravity=9.81)
+        q = torch.from_numpy(gaussian_bump_plane(k, k, 3, L, L)).to("cuda")
+        steps = max(10, min(400, int(4e9 / (q.numel() * 8 * 13))))
+        s = _plane_rk4_seconds(mesh, q, steps)
+        horiz.append({"elements": f"{k}x{k}", "ms_per_step": s * 1e3,
+                      "dof_updates_per_s": 3 * mesh.E * mesh.N * 4 / s})
+    vert = []
+    k = 300
+    q1 = torch.from_numpy(gaussian_bump_plane(k, k, 3, L, L)).to("cuda")
+    for nz in (1, 2, 4, 8, 16, 32, 64):
+        mesh = dg.Plane(k, k, 3, L, L, f=1.0e-4, gravity=9.81)
+        mesh.levels = nz
+        q = q1.unsqueeze(0).repeat(nz, 1, 1, 1).contiguous()
+        steps = max(5, min(100, int(4e9 / (q.numel() * 8 * 13))))
+        s = _plane_rk4_seconds(mesh, q, steps)
+        vert.append({"levels": nz, "ms_per_step": s * 1e3, "ms_per_step_per_level": s * 1e3 / nz,
+                     "dof_updates_per_s": 3 * mesh.E * mesh.N * nz * 4 / s})
+        del q
+    return {"workload": "f-plane r=3 FP64 RK4 (section 4.2 bump), section 5.2 scaling studies",
+            "horizontal": horiz, "vertical_300x300": vert}
+
+
 def profile_probe(args):
     """Short run for rocprofv3 counter passes: a few 3-stage cycles of the
     stage kernel, then device-to-device copies of a known size (the
@@ -401,6 +453,7 @@ def main():
         out["ensemble"] = ensemble_section()
         out["planar"] = planar_section()
         out["advection"] = advection_section()
+        out["scaling_studies"] = scaling_section()
         if os.path.exists(LEARNED_MODEL):
             out["learned"] = learned_section(LEARNED_MODEL)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)

@@ -149,6 +149,7 @@ static StageArgs<T, NP> stage_args(const StageLaunch &a) {
 
 template <typename T, int NP>
 static hipError_t launch_stage_t(const StageLaunch &a, hipStream_t s) {
+  if (a.levels < 1) return hipErrorInvalidValue;
   const StageArgs<T, NP> A = stage_args<T, NP>(a);
   if (a.variant == 1) {
     constexpr int GPW = ShapeH2<T, NP>::GPW;

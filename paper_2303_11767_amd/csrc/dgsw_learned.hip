@@ -292,6 +292,7 @@ int learned_stage(dg_ctx *ctx, const dg_learned *net, const LearnWs &t, const vo
   a.alpha_global = ctx->d.alpha_mode == DG_ALPHA_GLOBAL; a.combine = 0; a.c0 = 0.0; a.c1 = 1.0; a.dt = 0.0;
   a.periodic_y = ctx->periodic_y;
   a.variant = ctx->kernel;        // the same kernel layout as dg_rhs on this context
+  a.levels = 1;
   hipError_t e = dgsw::launch_stage(dt_, ctx->np, a, s);
   if (e != hipSuccess) return hip_fail(e, "r = 1 stage launch");
   // features, the whole network (hidden layers in LDS) and the per-element
