@@ -121,3 +121,6 @@ def test_null_arguments():
     out = (ctypes.c_double * 3)()
     assert lib.dg_mass(None, None, out, None) == -1
     assert lib.dg_set_forcing(None, None) == -1
+    assert lib.dg_set_levels(None, 2) == -1
+    k = ctypes.c_int32()
+    assert lib.dg_get_levels(None, ctypes.byref(k)) == -1
