@@ -139,3 +139,23 @@ def test_levels_argument_checks(dg):
     with pytest.raises(dg.DGError):
         ens.members[0].levels = 2
     assert ens.members[0].levels == 1
+
+
+@pytest.mark.parametrize("kernel", ["line", "half"])
+def test_layers_in_multiwave_workgroups(dg, kernel):
+    """180 x 90, r = 3 with 5 layers: enough wavefronts for the launch shape
+    of four wavefronts per workgroup (and, for the half layout, elements
+    packed across row ends); every layer equals the one-layer result, which
+    is itself checked against the oracle at this mesh."""
+    nl, nt, order, nz = 180, 90, 3, 5
+    say("levels multiwave", nl, nt, order, nz, kernel)
+    qa = band_limited_state(nl, nt, order, 16, 2)[0]
+    qb = band_limited_state(nl, nt, order, 8, 7)[0]
+    q = np.stack([qa, qb, qa, qb, qa])
+    mesh = dg.Mesh(nl, nt, order)
+    mesh.kernel = kernel
+    one = [mesh.rhs(torch.from_numpy(x).to("cuda")).cpu() for x in (qa, qb)]
+    mesh.levels = nz
+    got = mesh.rhs(torch.from_numpy(q).to("cuda")).cpu()
+    for k in range(nz):
+        assert torch.equal(got[k], one[k % 2]), k
