@@ -137,6 +137,14 @@ enum { DG_KERNEL_LINE = 0, DG_KERNEL_HALF = 1 };
 int dg_set_kernel(dg_ctx *ctx, int32_t kernel);
 int dg_get_kernel(const dg_ctx *ctx, int32_t *kernel);
 
+/* Pick the faster stage-kernel layout for this context by timing: two
+ * SSP-RK3 stages from q (read only) into work (dg_work_size(DG_SSP_RK3)
+ * values, overwritten) with each layout, the best of three repetitions after
+ * a warm-up, then dg_set_kernel with the faster one (*chosen, if not NULL,
+ * receives it).  Both layouts compute the same right-hand side up to
+ * rounding.  Synchronises hip_stream. */
+int dg_autotune(dg_ctx *ctx, const void *q, void *work, int32_t *chosen, void *hip_stream);
+
 /* Identical vertical layers (section 5.2.2: decoupled two-dimensional problems
  * stacked in the vertical and solved side by side).  After this call every
  * state-shaped buffer of the context (q, dqdt, q0, out, the work buffers and

@@ -117,6 +117,15 @@ class Mesh:
     def kernel(self, name):
         check(self._lib.dg_set_kernel(self._ctx, {"line": 0, "half": 1}[name]))
 
+    def autotune(self, q, stream=None):
+        """Time both stage-kernel layouts on q (read only) and keep the
+        faster (dg_autotune); returns its name.  Synchronises the stream."""
+        work = self.empty_work(DG_SSP_RK3, q.device)
+        k = ctypes.c_int32()
+        check(self._lib.dg_autotune(self._ctx, self._ptr(q, "q"), self._ptr(work, "work", self.work_size()),
+                                    ctypes.byref(k), _stream_handle(stream)))
+        return "half" if k.value == 1 else "line"
+
     # -- identical vertical layers (dg_set_levels)
     @property
     def levels(self):

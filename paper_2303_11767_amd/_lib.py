@@ -23,7 +23,8 @@ ERROR_NAMES = {
 }
 
 # every symbol include/dgsw.h declares
-EXPORTS = ("dg_init_mesh", "dg_init_plane", "dg_set_kernel", "dg_get_kernel", "dg_set_levels",
+EXPORTS = ("dg_init_mesh", "dg_init_plane", "dg_set_kernel", "dg_get_kernel", "dg_autotune",
+           "dg_set_levels",
            "dg_get_levels", "dg_free", "dg_state_size", "dg_work_size", "dg_min_width", "dg_rhs",
            "dg_rk_stage", "dg_rk_step", "dg_mass", "dg_set_forcing", "dg_last_error",
            "dg_ens_init", "dg_ens_free", "dg_ens_state_size", "dg_ens_offsets", "dg_ens_member",

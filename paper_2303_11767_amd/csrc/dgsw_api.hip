@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -227,6 +228,59 @@ int dg_get_kernel(const dg_ctx *ctx, int32_t *kernel) {
   if (!ctx || !kernel) return fail(DG_EINVAL, "NULL argument");
   *kernel = ctx->kernel;
   return DG_OK;
+}
+
+static int stage(dg_ctx *c, const void *q, const void *q0, void *out, int combine, double c0,
+                 double c1, double dt, hipStream_t s);
+
+int dg_autotune(dg_ctx *ctx, const void *q, void *work, int32_t *chosen, void *hip_stream) {
+  if (!ctx || !q || !work) return fail(DG_EINVAL, "NULL argument");
+  if (!aligned16(q) || !aligned16(work)) return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
+  const size_t bytes = ctx->state_n * ctx->elem_bytes;
+  {
+    const char *a = static_cast<const char *>(q);
+    const char *b = static_cast<const char *>(work);
+    if (a < b + 2 * bytes && b < a + bytes) return fail(DG_EINVAL, "q and work overlap");
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  char *w0 = static_cast<char *>(work);
+  char *w1 = w0 + bytes;
+  hipEvent_t ev[2];
+  if (hipEventCreate(&ev[0]) != hipSuccess) return fail(DG_EHIP, "hipEventCreate");
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return fail(DG_EHIP, "hipEventCreate");
+  }
+  const int keep = ctx->kernel;
+  float best = 1e30f;
+  int best_k = keep, rc = DG_OK;
+  for (int k : {DG_KERNEL_LINE, DG_KERNEL_HALF}) {
+    ctx->kernel = k;
+    float t_best = 1e30f;
+    for (int rep = 0; rep < 4 && rc == DG_OK; ++rep) {
+      hipError_t e = hipEventRecord(ev[0], s);
+      if (e != hipSuccess) { rc = hip_fail(e, "hipEventRecord"); break; }
+      if ((rc = stage(ctx, q, nullptr, w0, 1, 0.0, 1.0, 0.0, s)) != DG_OK) break;
+      if ((rc = stage(ctx, w0, q, w1, 1, 0.75, 0.25, 0.0, s)) != DG_OK) break;
+      if ((e = hipEventRecord(ev[1], s)) != hipSuccess || (e = hipEventSynchronize(ev[1])) != hipSuccess) {
+        rc = hip_fail(e, "autotune timing");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (rep > 0) t_best = std::min(t_best, ms);   // the first repetition warms up
+    }
+    if (rc != DG_OK) break;
+    if (t_best < best) {
+      best = t_best;
+      best_k = k;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  ctx->kernel = rc == DG_OK ? best_k : keep;
+  if (rc == DG_OK && chosen) *chosen = best_k;
+  return rc;
 }
 
 int dg_set_levels(dg_ctx *ctx, int32_t n_levels) {

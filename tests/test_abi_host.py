@@ -122,5 +122,6 @@ def test_null_arguments():
     assert lib.dg_mass(None, None, out, None) == -1
     assert lib.dg_set_forcing(None, None) == -1
     assert lib.dg_set_levels(None, 2) == -1
+    assert lib.dg_autotune(None, None, None, None, None) == -1
     k = ctypes.c_int32()
     assert lib.dg_get_levels(None, ctypes.byref(k)) == -1

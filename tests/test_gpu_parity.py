@@ -99,6 +99,27 @@ def test_rhs_c3(dg, dtype, kernel):
     check_rhs(dg, 360, 180, 5, dtype, L=32, seed=3, kernel=kernel)
 
 
+@pytest.mark.parametrize("dims", [(90, 45, 2, "f32"), (180, 90, 3, "f64")])
+def test_autotune_reads_q_only_and_keeps_a_layout(dg, dims):
+    """dg_autotune times both layouts on q without changing it and leaves
+    the context on the one it reports."""
+    nl, nt, r, dtype = dims
+    say("autotune", dims)
+    q, _ = band_limited_state(nl, nt, r, 8, 11)
+    mesh = make(dg, nl, nt, r, dtype)
+    qd = to_dev(q, dtype)
+    before = qd.clone()
+    name = mesh.autotune(qd)
+    say("  chose", name)
+    assert name in ("line", "half") and mesh.kernel == name
+    assert torch.equal(qd, before)
+    got = mesh.rhs(qd)
+    other = "half" if name == "line" else "line"
+    mesh.kernel = other
+    mesh.kernel = name
+    assert torch.equal(mesh.rhs(qd), got)
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_rhs_degenerate_meshes(dg, kernel):
     """One row (both edges are poles), one column (the element is its own
