@@ -511,10 +511,12 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
 // as above but only half of each line's outputs (indices h K0 .. h K0 + K0 - 1,
 // K0 = ceil(NP / 2)), and half of the edge work: h = 0 the east and north
 // edges, h = 1 the west and south edges (traces, neighbour loads and Rusanov
-// fluxes).  Twice the wavefronts with about half the instructions and
-// registers each: more latency hiding where one wavefront per SIMD is all
-// a mesh provides, and higher occupancy on large meshes.  The two halves'
-// partial volume sums are added in LDS (h = 0 writes, h = 1 accumulates).
+// fluxes).  In the volume both halves evaluate the fluxes at all NP nodes of
+// column t and each contracts them for its own K0 outputs, so no partial
+// sums cross between the halves (only the latitude edge fluxes, through
+// LDS).  Twice the wavefronts with about 0.6x the instructions and 0.7x the
+// registers each: more latency hiding where one wavefront per SIMD is all a
+// mesh provides, and higher occupancy on large meshes.
 template <typename T, int NP>
 struct ShapeH2 {
   static constexpr int N = NP * NP;
@@ -523,7 +525,10 @@ struct ShapeH2 {
   static constexpr int K0 = (NP + 1) / 2;
   static constexpr int NB = 3 * (NP + 2) * NP;
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
-  static constexpr int SH = cmax(NB + 12 * NP, 6 * NP * NP + 6 * NP);
+  // second phase: the volume outputs [3][2][NP][NP], then the longitude and
+  // latitude edge fluxes of both halves [3][2][NP] each
+  static constexpr int oFX = 6 * NP * NP, oGY = oFX + 6 * NP;
+  static constexpr int SH = cmax(NB + 12 * NP, oGY + 6 * NP);
   static constexpr int SLOTS = GPW + (SPARE ? 1 : 0);
   // LDS copy of the tables: the GlobTab prefix (B, D, Pp, Pm, w), then the
   // whole RowTab of the wavefront's first row and of the row after it (a
@@ -698,9 +703,9 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
   }
   wave_sync();
 
-  // ---- eta pass: nodal values of column p = t at this half's nodes s, own
-  // and neighbour traces of this half's two edges
-  T nd[3][K0], trX[3], trY[3], nbX[3], nbY[3];
+  // ---- eta pass: nodal values of column p = t at all its nodes s, own and
+  // neighbour traces of this half's two edges
+  T nd[3][NP], trX[3], trY[3], nbX[3], nbY[3];
   T bt[NP];
 #pragma unroll
   for (int k = 0; k < NP; ++k) bt[k] = tab[S_::oB + t * NP + k];          // P~_k(xi_t)
@@ -710,11 +715,11 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
 #pragma unroll
     for (int b = 0; b < NP; ++b) col[b] = S[(v * (NP + 2) + t) * NP + b];
 #pragma unroll
-    for (int k = 0; k < K0; ++k) {
+    for (int s = 0; s < NP; ++s) {
       T acc = T(0);
 #pragma unroll
-      for (int b = 0; b < NP; ++b) acc += col[b] * BP[k][b];
-      nd[v][k] = acc;
+      for (int b = 0; b < NP; ++b) acc += col[b] * gt->B[s][b];
+      nd[v][s] = acc;
     }
     T ay = T(0), ax = T(0), nx = T(0), ny = T(0);
 #pragma unroll
@@ -745,25 +750,35 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
   for (int v = 0; v < 3; ++v) {
     FhX[v] *= invR;
     GhY[v] = hasY ? GhY[v] * fY : T(0);
+    S[S_::oFX + (v * 2 + h) * NP + t] = FhX[v];   // read back in the last xi pass
+    S[S_::oGY + (v * 2 + h) * NP + t] = GhY[v];   // the other half's latitude edge
+  }
+  wave_sync();
+  T GhN[3], GhS[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    const T other = S[S_::oGY + (v * 2 + 1 - h) * NP + t];
+    GhN[v] = h ? other : GhY[v];
+    GhS[v] = h ? GhY[v] : other;
   }
 
-  // ---- volume: fluxes and sources at nodes (t, s) of this half, partial
-  // contraction over s
-  T ZD[3][NP], ZG[3][NP], ZS[2][NP];
+  // ---- volume: fluxes and sources at all nodes (t, s) of column t,
+  // contracted over s for this half's outputs b = h K0 + kb
+  T ZD[3][K0], ZG[3][K0], ZS[2][K0];
 #pragma unroll
   for (int v = 0; v < 3; ++v)
 #pragma unroll
-    for (int b = 0; b < NP; ++b) { ZD[v][b] = T(0); ZG[v][b] = T(0); }
+    for (int kb = 0; kb < K0; ++kb) { ZD[v][kb] = T(0); ZG[v][kb] = T(0); }
 #pragma unroll
   for (int v = 0; v < 2; ++v)
 #pragma unroll
-    for (int b = 0; b < NP; ++b) ZS[v][b] = T(0);
+    for (int kb = 0; kb < K0; ++kb) ZS[v][kb] = T(0);
+  int bh[K0];
 #pragma unroll
-  for (int k = 0; k < K0; ++k) {
-    const int s_raw = h * K0 + k;
-    const int s = s_raw < NP ? s_raw : NP - 1;
-    const bool valid = NP % 2 == 0 || s_raw < NP;
-    const T dh = nd[0][k], hu = nd[1][k], hv = nd[2][k];
+  for (int kb = 0; kb < K0; ++kb) bh[kb] = h * K0 + kb < NP ? h * K0 + kb : NP - 1;
+#pragma unroll
+  for (int s = 0; s < NP; ++s) {
+    const T dh = nd[0][s], hu = nd[1][s], hv = nd[2][s];
     const T hh = dh + H;
     const T rh = dg_rcp(hh);
     const T u = hu * rh, vv = hv * rh;
@@ -774,49 +789,26 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
     const T G0 = hv * cR, G1 = hv * u * cR, G2 = (hv * vv + pr) * cR;
     const T C = tab[ro + S_::rFc + s] + u * tab[ro + S_::rSnR + s];
     const T S1 = C * hv, S2 = -pr * tab[ro + S_::rStR + s] - C * hu;
-    const T m = valid ? T(1) : T(0);
 #pragma unroll
-    for (int b = 0; b < NP; ++b) {
-      const T bm = m * tab[ro + S_::rBM + s * NP + b], dm = m * tab[ro + S_::rDM + s * NP + b];
-      ZD[0][b] += F0 * bm; ZD[1][b] += F1 * bm; ZD[2][b] += F2 * bm;
-      ZG[0][b] += G0 * dm; ZG[1][b] += G1 * dm; ZG[2][b] += G2 * dm;
-      ZS[0][b] += S1 * bm; ZS[1][b] += S2 * bm;
+    for (int kb = 0; kb < K0; ++kb) {
+      const T bm = tab[ro + S_::rBM + s * NP + bh[kb]], dm = tab[ro + S_::rDM + s * NP + bh[kb]];
+      ZD[0][kb] += F0 * bm; ZD[1][kb] += F1 * bm; ZD[2][kb] += F2 * bm;
+      ZG[0][kb] += G0 * dm; ZG[1][kb] += G1 * dm; ZG[2][kb] += G2 * dm;
+      ZS[0][kb] += S1 * bm; ZS[1][kb] += S2 * bm;
     }
   }
   const T wt = tab[S_::oW + t], cF = gt->cF, cG = gt->cG;
-  // this half's latitude surface term: - G^_N MN (h = 0), + G^_S MS (h = 1)
-  T PV[3][NP], PG[3][NP];
 #pragma unroll
   for (int v = 0; v < 3; ++v)
 #pragma unroll
-    for (int b = 0; b < NP; ++b) {
-      const T my = tab[ro + S_::rMN + h * NP + b];
-      const T zg = ZG[v][b] + (h ? GhY[v] : -GhY[v]) * my;
-      const T zs = v == 0 ? T(0) : ZS[v - 1][b];
-      PV[v][b] = cF * wt * ZD[v][b];
-      PG[v][b] = wt * (cG * zg + zs);
+    for (int kb = 0; kb < K0; ++kb) {
+      if (NP % 2 != 0 && h * K0 + kb >= NP) continue;   // the odd-order tail slot
+      const int b = bh[kb];
+      const T zg = ZG[v][kb] - (GhN[v] * tab[ro + S_::rMN + b] - GhS[v] * tab[ro + S_::rMS + b]);
+      const T zs = v == 0 ? T(0) : ZS[v - 1][kb];
+      S[((v * 2 + 0) * NP + t) * NP + b] = cF * wt * ZD[v][kb];
+      S[((v * 2 + 1) * NP + t) * NP + b] = wt * (cG * zg + zs);
     }
-  if (h == 0) {
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-      for (int b = 0; b < NP; ++b) {
-        S[((v * 2 + 0) * NP + t) * NP + b] = PV[v][b];
-        S[((v * 2 + 1) * NP + t) * NP + b] = PG[v][b];
-      }
-  }
-#pragma unroll
-  for (int v = 0; v < 3; ++v) S[6 * NP * NP + (v * 2 + h) * NP + t] = FhX[v];
-  wave_sync();
-  if (h == 1) {
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-      for (int b = 0; b < NP; ++b) {
-        S[((v * 2 + 0) * NP + t) * NP + b] += PV[v][b];
-        S[((v * 2 + 1) * NP + t) * NP + b] += PG[v][b];
-      }
-  }
   wave_sync();
 
   // ---- epilogue operands for this half's modes a = h K0 + k of row b = t
