@@ -6,11 +6,19 @@ namespace dgsw {
 
 // PK: wavefront w of a layer takes the GPW consecutive elements from w GPW on,
 // across row ends (needs GPW <= n_lon; ceil(E / GPW) wavefronts); otherwise
-// row-aligned segments, segs per row.  At least two wavefronts per SIMD: the
-// register budget stays within 256 (the FP64 r >= 5 cases sit at that edge,
-// where a few spilled values cost far less than half the occupancy).
+// row-aligned segments, segs per row.  One wavefront per workgroup (its LDS
+// then fits 15 wavefronts per CU at FP64 r = 3).  Register budget: four
+// wavefronts per SIMD (128 registers) at FP64 r = 3, where the kernel needs
+// 130-138 and the last few cost nothing measurable; two (256) elsewhere, which
+// keeps the FP64 r >= 5 cases, at the edge of 256, from spilling into
+// accumulation registers and halving their occupancy.
+template <typename T, int NP>
+struct H2Occ {
+  static constexpr int value = sizeof(T) == 8 && NP == 4 ? 4 : 2;
+};
+
 template <typename T, int NP, int WPB, int CM, bool PK>
-__global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * WPB) void k_dg_stage_h2(
+__global__ __attribute__((amdgpu_waves_per_eu(H2Occ<T, NP>::value))) __launch_bounds__(64 * WPB) void k_dg_stage_h2(
     StageArgs<T, NP> A, int segs) {
   using S_ = ShapeH2<T, NP>;
   __shared__ T tab_all[WPB][S_::TB];
@@ -159,23 +167,16 @@ static hipError_t launch_stage_t(const StageLaunch &a, hipStream_t s) {
     const bool packed = GPW <= a.n_lon && a.n_lon % GPW != 0;
     const int per = packed ? (a.n_lon * a.n_lat + GPW - 1) / GPW : segs * a.n_lat;
     const int waves = per * a.levels;
-    const bool big = waves >= 4096;
-    const dim3 grid(big ? (waves + 3) / 4 : waves), block(big ? 256 : 64);
-#define DGSW_H2(WPB_, CM_)                                                                   \
-  do {                                                                                       \
-    if (packed) hipLaunchKernelGGL((k_dg_stage_h2<T, NP, WPB_, CM_, true>), grid, block, 0, s, A, segs); \
-    else hipLaunchKernelGGL((k_dg_stage_h2<T, NP, WPB_, CM_, false>), grid, block, 0, s, A, segs);      \
+    const dim3 grid(waves), block(64);
+#define DGSW_H2(CM_)                                                                      \
+  do {                                                                                    \
+    if (packed) hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 1, CM_, true>), grid, block, 0, s, A, segs); \
+    else hipLaunchKernelGGL((k_dg_stage_h2<T, NP, 1, CM_, false>), grid, block, 0, s, A, segs);      \
   } while (0)
     switch (a.combine) {
-      case 0:
-        if (big) DGSW_H2(4, 0); else DGSW_H2(1, 0);
-        break;
-      case 1:
-        if (big) DGSW_H2(4, 1); else DGSW_H2(1, 1);
-        break;
-      case 2:
-        if (big) DGSW_H2(4, 2); else DGSW_H2(1, 2);
-        break;
+      case 0: DGSW_H2(0); break;
+      case 1: DGSW_H2(1); break;
+      case 2: DGSW_H2(2); break;
       default:
         return hipErrorInvalidValue;
     }
