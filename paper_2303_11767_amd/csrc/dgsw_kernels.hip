@@ -8,17 +8,18 @@ namespace dgsw {
 // across row ends (needs GPW <= n_lon; ceil(E / GPW) wavefronts); otherwise
 // row-aligned segments, segs per row.  One wavefront per workgroup (its LDS
 // then fits 15 wavefronts per CU at FP64 r = 3).  Register budget: four
-// wavefronts per SIMD (128 registers) at FP64 r = 3, where the kernel needs
-// 130-138 and the last few cost nothing measurable; two (256) elsewhere, which
+// wavefronts per SIMD (128 registers) at FP64 r = 3 with the one-state
+// combinations, where the kernel needs 130-138 and the last few cost nothing
+// measurable (the RK4 combination would spill); two (256) elsewhere, which
 // keeps the FP64 r >= 5 cases, at the edge of 256, from spilling into
 // accumulation registers and halving their occupancy.
-template <typename T, int NP>
+template <typename T, int NP, int CM>
 struct H2Occ {
-  static constexpr int value = sizeof(T) == 8 && NP == 4 ? 4 : 2;
+  static constexpr int value = sizeof(T) == 8 && NP == 4 && CM != 2 ? 4 : 2;
 };
 
 template <typename T, int NP, int WPB, int CM, bool PK>
-__global__ __attribute__((amdgpu_waves_per_eu(H2Occ<T, NP>::value))) __launch_bounds__(64 * WPB) void k_dg_stage_h2(
+__global__ __attribute__((amdgpu_waves_per_eu(H2Occ<T, NP, CM>::value))) __launch_bounds__(64 * WPB) void k_dg_stage_h2(
     StageArgs<T, NP> A, int segs) {
   using S_ = ShapeH2<T, NP>;
   __shared__ T tab_all[WPB][S_::TB];
