@@ -290,8 +290,13 @@ int dg_set_levels(dg_ctx *ctx, int32_t n_levels) {
   if (n_levels < 1 || n_levels > 65535) return fail(DG_EINVAL, "n_levels must be in 1..65535");
   if (ctx->member && n_levels != 1)
     return fail(DG_EUNSUPPORTED, "an ensemble member holds one layer");
-  // wavefronts of one layer in the denser (half-line) layout
-  const int64_t per = (int64_t)dgsw::waves_per_row(ctx->np, ctx->d.n_lon) * 2 * ctx->d.n_lat;
+  // wavefronts of one layer in either layout (the half-line layout row-aligned
+  // or packed across rows), bounded so that all layers fit one launch
+  const int64_t gh = 64 / (2 * ctx->np);
+  const int64_t E = (int64_t)ctx->d.n_lon * ctx->d.n_lat;
+  int64_t per = (int64_t)dgsw::waves_per_row(ctx->np, ctx->d.n_lon) * ctx->d.n_lat;
+  per = std::max(per, (ctx->d.n_lon + gh - 1) / gh * ctx->d.n_lat);
+  per = std::max(per, (E + gh - 1) / gh);
   if (per * n_levels >= ((int64_t)1 << 31)) return fail(DG_EINVAL, "too many layers for one launch");
   ctx->levels = n_levels;
   ctx->state_n = ctx->level_n * n_levels;
