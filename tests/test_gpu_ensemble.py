@@ -7,7 +7,7 @@ import sys
 import numpy as np
 import pytest
 
-from dg_inputs import band_limited_state
+from dg_inputs import band_limited_state, ensemble_members, lake_at_rest_state
 from oracle import SphereDG
 from parity_util import TOL, errors
 
@@ -153,3 +153,36 @@ def test_graph_replays_match_eager(dg):
         torch.cuda.synchronize()
         assert torch.equal(qm, qref), rep
     gm.close()
+
+
+def test_full_ensemble_sampled_members_vs_oracle(dg):
+    """The 64-member FP32 ensemble of the benchmark (orders 2-4, 90x45 ..
+    360x180) in its autotuned launch configuration: three members (the first,
+    the first of the largest shape and one of another order) hold seeded
+    band-limited states and are checked against the oracle one by one; the
+    other members hold a lake at rest and must stay finite."""
+    mem = ensemble_members(64, seed=4)
+    say("full ensemble", len(mem), "members")
+    ens = dg.Ensemble(mem, dtype="f32", h_ref=1e4)
+    q = ens.empty_state()
+    big = next(k for k, m in enumerate(mem) if (m["n_lon"], m["n_lat"], m["order"]) == (360, 180, 4))
+    other = next(k for k, m in enumerate(mem) if m["order"] != mem[0]["order"] and k != big)
+    sampled = {0, big, other}
+    states = {}
+    for k, (m, v) in enumerate(zip(ens.members, ens.views(q))):
+        if k in sampled:
+            qh, _ = band_limited_state(m.n_lon, m.n_lat, m.order, 8, 7000 + k)
+            states[k] = qh
+        else:
+            qh = lake_at_rest_state(m.n_lon, m.n_lat, m.order)
+        v.copy_(torch.from_numpy(qh).to(v.dtype))
+    ens.autotune(q, ens.empty_work())
+    out = ens.rhs(q)
+    assert torch.isfinite(out).all()
+    for k in sorted(sampled):
+        m = ens.members[k]
+        qin = states[k].astype(np.float32).astype(np.float64)
+        o = SphereDG(m.n_lon, m.n_lat, m.order)
+        comp, _ = errors(ens.views(out)[k].cpu().numpy(), o.rhs(qin), o.rhs_scale(qin))
+        say("  member", k, m.n_lon, m.n_lat, m.order, "componentwise", comp)
+        assert np.all(comp <= TOL["f32"]), (k, comp)
