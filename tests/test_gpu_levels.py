@@ -159,3 +159,22 @@ def test_layers_in_multiwave_workgroups(dg, kernel):
     got = mesh.rhs(torch.from_numpy(q).to("cuda")).cpu()
     for k in range(nz):
         assert torch.equal(got[k], one[k % 2]), k
+
+
+def test_autotune_with_layers(dg):
+    """dg_autotune on a three-layer state: reads it only, keeps a layout, and
+    the layers still agree bitwise with one-layer runs of that layout."""
+    nl, nt, order, nz = 40, 20, 3, 3
+    say("levels autotune", nl, nt, order, nz)
+    q = layers(nl, nt, order, nz, 800)
+    mesh = dg.Mesh(nl, nt, order)
+    mesh.levels = nz
+    qd = torch.from_numpy(q).to("cuda")
+    before = qd.clone()
+    name = mesh.autotune(qd)
+    assert torch.equal(qd, before) and mesh.kernel == name
+    got = mesh.rhs(qd).cpu()
+    single = dg.Mesh(nl, nt, order)
+    single.kernel = name
+    for k in range(nz):
+        assert torch.equal(got[k], single.rhs(torch.from_numpy(q[k]).to("cuda")).cpu()), k
