@@ -450,6 +450,11 @@ def main():
         return
     out = run(args)
     if not args.no_extras:
+        # the same workload and loop in the other precision the configuration names
+        other = argparse.Namespace(**vars(args))
+        other.dtype = "f32" if args.dtype == "f64" else "f64"
+        o = run(other)
+        out["other_precision"] = {k: o[k] for k in ("dtype", "value", "unit", "ms_per_step", "roofline")}
         out["ensemble"] = ensemble_section()
         out["planar"] = planar_section()
         out["advection"] = advection_section()
