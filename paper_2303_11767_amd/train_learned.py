@@ -242,6 +242,39 @@ def judge(args, model, seeds, t_eval, dtype="f64"):
     }
 
 
+KAPPAS = (1.0, 2.0, 4.0, 8.0, 16.0, 1.0e30)
+
+
+def select_kappa(args):
+    """The trust bound is a tuning choice of the fallback, so it is chosen on
+    validation seeds (disjoint from the training seeds 0.. and the held-out
+    seeds 200..): the smallest kappa whose learned error is within 5 % of the
+    best one, recorded in the model's metadata; then the held-out judge."""
+    model, meta = load_model(args.select_kappa)
+    seeds = range(args.val_seed0, args.val_seed0 + args.val)
+    errs = {}
+    for k in KAPPAS:
+        rep = judge(argparse.Namespace(kappa=k), model, seeds, args.t_eval)
+        errs[k] = rep["h_rms_error_m"]["learned"]
+        log(f"kappa {k:g}: learned {errs[k]:.4e} m (plain r1 {rep['h_rms_error_m']['r1']:.4e} m)")
+    best = min(errs.values())
+    chosen = min(k for k, e in errs.items() if e <= 1.05 * best)
+    meta["kappa"] = chosen
+    meta["kappa_selection"] = {"seeds": list(seeds), "t_eval_s": args.t_eval,
+                               "learned_h_rms_m": {f"{k:g}": e for k, e in errs.items()}}
+    save(args.select_kappa, model, meta)
+    args.kappa = chosen
+    report = judge(args, model, range(200, 200 + args.heldout), args.t_eval)
+    report["model"] = os.path.basename(args.select_kappa)
+    report["kappa_selection"] = meta["kappa_selection"]
+    report["training"] = {k: meta[k] for k in ("traj", "snapshots", "t_train_s", "steps", "batch", "lr")
+                          if k in meta}
+    log(json.dumps(report))
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump(report, f, indent=1)
+
+
 def save(path, model, meta):
     np.savez(path, **{k: v.detach().cpu().numpy() for k, v in model.items()},
              meta=np.array(json.dumps(meta)))
@@ -272,7 +305,15 @@ def main():
     ap.add_argument("--report", default=None)
     ap.add_argument("--judge-only", default=None, metavar="MODEL",
                     help="judge a saved model (no training)")
+    ap.add_argument("--select-kappa", default=None, metavar="MODEL",
+                    help="pick the trust bound kappa of a saved model on validation seeds "
+                         "(--val-seed0, --val), store it in the model, then judge it")
+    ap.add_argument("--val-seed0", type=int, default=300)
+    ap.add_argument("--val", type=int, default=4)
     args = ap.parse_args()
+    if args.select_kappa:
+        select_kappa(args)
+        return
     if args.judge_only:
         model, meta = load_model(args.judge_only)
         report = judge(args, model, range(200, 200 + args.heldout), args.t_eval)

@@ -246,3 +246,22 @@ def test_learned_rk_step_runs(dg):
         m1 = mesh.mass(q)[0]
         assert np.isfinite(m1)
         assert abs(m1 - m0) <= (1e-13 if dtype == "f64" else 1e-6) * abs(m0)
+
+
+def test_stored_model_gains_over_plain_r1(dg):
+    """The committed network, judged on a held-out seed by the plain r = 5
+    solver (10 s horizon, the model's stored trust bound): its h error is
+    well below plain r = 1's and below the untrained network's."""
+    import argparse
+    import os
+    from paper_2303_11767_amd import train_learned as tl
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2303_11767_amd", "models", "learned_r1_360x180.npz")
+    model, meta = tl.load_model(path)
+    say("stored model gain, kappa", meta["kappa"])
+    rep = tl.judge(argparse.Namespace(kappa=meta["kappa"]), model, [200], 10.0)
+    e = rep["h_rms_error_m"]
+    say("  h rms", e)
+    assert e["learned"] * 2 < e["r1"]
+    assert e["learned"] * 2 < e["untrained"]
+    assert rep["throughput_learned_over_r4"] > 5
