@@ -292,10 +292,10 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--traj", type=int, default=200)
     ap.add_argument("--seed0", type=int, default=0)
-    ap.add_argument("--snapshots", type=int, default=3)
+    ap.add_argument("--snapshots", type=int, default=5)
     ap.add_argument("--t-train", type=float, default=30.0)
     ap.add_argument("--rows-per-snapshot", type=int, default=8192)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--kappa", type=float, default=1.0)
