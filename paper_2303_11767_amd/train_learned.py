@@ -298,7 +298,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--kappa", type=float, default=1.0)
+    ap.add_argument("--kappa", type=float, default=None,
+                    help="trust bound of the fallback (default: the model's stored one; 1 for a new model)")
     ap.add_argument("--heldout", type=int, default=10)
     ap.add_argument("--t-eval", type=float, default=30.0)
     ap.add_argument("--out", default="learned_r1_360x180.npz")
@@ -316,6 +317,8 @@ def main():
         return
     if args.judge_only:
         model, meta = load_model(args.judge_only)
+        if args.kappa is None:
+            args.kappa = meta.get("kappa", 1.0)
         report = judge(args, model, range(200, 200 + args.heldout), args.t_eval)
         report["model"] = os.path.basename(args.judge_only)
         log(json.dumps(report))
@@ -323,6 +326,8 @@ def main():
             with open(args.report, "w") as f:
                 json.dump(report, f, indent=1)
         return
+    if args.kappa is None:
+        args.kappa = 1.0
     wb = Workbench("f32")
     t0 = time.time()
     X, T, stats = build_dataset(args, wb)
