@@ -254,14 +254,14 @@ def ensemble_section(steps=10):
 
 
 def learned_section(model_path, seeds=(200, 201), t_eval=10.0):
-    """The learned r = 1 form against plain r = 1 and plain r = 4, judged by
+    """The learned r = 1 form against plain r = 1 and plain r = 4, evaluated against
     the plain r = 5 solver (FP64, held-out seeds), with wall-clock."""
     import argparse as _ap
     import contextlib
     from paper_2303_11767_amd import train_learned as tl
     model, meta = tl.load_model(model_path)
     with contextlib.redirect_stdout(sys.stderr):      # stdout carries only the JSON line
-        rep = tl.judge(_ap.Namespace(kappa=meta.get("kappa", 1.0)), model, seeds, t_eval)
+        rep = tl.evaluate(_ap.Namespace(kappa=meta.get("kappa", 1.0)), model, seeds, t_eval)
     rep["model"] = os.path.relpath(model_path, ROOT)
     return rep
 

@@ -1,4 +1,4 @@
-"""Train and judge the learned r = 1 right-hand-side correction.
+"""Train and evaluate the learned r = 1 right-hand-side correction.
 
     python -m paper_2303_11767_amd.train_learned [--traj 200] [--out model.npz]
 
@@ -12,7 +12,7 @@ the 3 x 3 element stencil of P1 q4 (dg_features), standardised per feature;
 targets are standardised per latitude row.  The network is trained with the
 library's own forward/backward/Adam kernels (dg_mlp_train_step).
 
-Judge: on held-out seeds, the truth is the plain r = 5 solver from the same
+Evaluation: on held-out seeds, the truth is the plain r = 5 solver from the same
 initial polynomial field; the error of a method is the RMS over the sphere of
 P1 h_method - P1 h_truth at the horizon.  Compared: plain r = 1, learned r = 1
 (trained), learned r = 1 with an untrained network, plain r = 4; wall-clock
@@ -168,7 +168,7 @@ def fit(args, wb, X, T):
     return params, hist
 
 
-def judge(args, model, seeds, t_eval, dtype="f64"):
+def evaluate(args, model, seeds, t_eval, dtype="f64"):
     """Errors at the horizon against the r = 5 truth, and wall-clock."""
     import torch
     import paper_2303_11767_amd as dg
@@ -249,12 +249,12 @@ def select_kappa(args):
     """The trust bound is a tuning choice of the fallback, so it is chosen on
     validation seeds (disjoint from the training seeds 0.. and the held-out
     seeds 200..): the smallest kappa whose learned error is within 5 % of the
-    best one, recorded in the model's metadata; then the held-out judge."""
+    best one, recorded in the model's metadata; then the held-out evaluation."""
     model, meta = load_model(args.select_kappa)
     seeds = range(args.val_seed0, args.val_seed0 + args.val)
     errs = {}
     for k in KAPPAS:
-        rep = judge(argparse.Namespace(kappa=k), model, seeds, args.t_eval)
+        rep = evaluate(argparse.Namespace(kappa=k), model, seeds, args.t_eval)
         errs[k] = rep["h_rms_error_m"]["learned"]
         log(f"kappa {k:g}: learned {errs[k]:.4e} m (plain r1 {rep['h_rms_error_m']['r1']:.4e} m)")
     best = min(errs.values())
@@ -264,7 +264,7 @@ def select_kappa(args):
                                "learned_h_rms_m": {f"{k:g}": e for k, e in errs.items()}}
     save(args.select_kappa, model, meta)
     args.kappa = chosen
-    report = judge(args, model, range(200, 200 + args.heldout), args.t_eval)
+    report = evaluate(args, model, range(200, 200 + args.heldout), args.t_eval)
     report["model"] = os.path.basename(args.select_kappa)
     report["kappa_selection"] = meta["kappa_selection"]
     report["training"] = {k: meta[k] for k in ("traj", "snapshots", "t_train_s", "steps", "batch", "lr")
@@ -304,23 +304,23 @@ def main():
     ap.add_argument("--t-eval", type=float, default=30.0)
     ap.add_argument("--out", default="learned_r1_360x180.npz")
     ap.add_argument("--report", default=None)
-    ap.add_argument("--judge-only", default=None, metavar="MODEL",
-                    help="judge a saved model (no training)")
+    ap.add_argument("--evaluate-only", default=None, metavar="MODEL",
+                    help="evaluate a saved model (no training)")
     ap.add_argument("--select-kappa", default=None, metavar="MODEL",
                     help="pick the trust bound kappa of a saved model on validation seeds "
-                         "(--val-seed0, --val), store it in the model, then judge it")
+                         "(--val-seed0, --val), store it in the model, then evaluate it")
     ap.add_argument("--val-seed0", type=int, default=300)
     ap.add_argument("--val", type=int, default=4)
     args = ap.parse_args()
     if args.select_kappa:
         select_kappa(args)
         return
-    if args.judge_only:
-        model, meta = load_model(args.judge_only)
+    if args.evaluate_only:
+        model, meta = load_model(args.evaluate_only)
         if args.kappa is None:
             args.kappa = meta.get("kappa", 1.0)
-        report = judge(args, model, range(200, 200 + args.heldout), args.t_eval)
-        report["model"] = os.path.basename(args.judge_only)
+        report = evaluate(args, model, range(200, 200 + args.heldout), args.t_eval)
+        report["model"] = os.path.basename(args.evaluate_only)
         log(json.dumps(report))
         if args.report:
             with open(args.report, "w") as f:
@@ -338,7 +338,7 @@ def main():
             "t_train_s": args.t_train, "steps": args.steps, "batch": args.batch, "lr": args.lr,
             "loss_history": hist, "kappa": args.kappa}
     save(args.out, model, meta)
-    report = judge(args, model, range(200, 200 + args.heldout), args.t_eval)
+    report = evaluate(args, model, range(200, 200 + args.heldout), args.t_eval)
     report["training"] = {k: meta[k] for k in ("traj", "snapshots", "t_train_s", "steps", "batch", "lr")}
     report["final_loss"] = hist[-1][1]
     log(json.dumps(report))

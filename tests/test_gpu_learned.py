@@ -249,7 +249,7 @@ def test_learned_rk_step_runs(dg):
 
 
 def test_stored_model_gains_over_plain_r1(dg):
-    """The committed network, judged on a held-out seed by the plain r = 5
+    """The committed network, evaluated on a held-out seed against the plain r = 5
     solver (10 s horizon, the model's stored trust bound): its h error is
     well below plain r = 1's and below the untrained network's."""
     import argparse
@@ -259,7 +259,7 @@ def test_stored_model_gains_over_plain_r1(dg):
                         "paper_2303_11767_amd", "models", "learned_r1_360x180.npz")
     model, meta = tl.load_model(path)
     say("stored model gain, kappa", meta["kappa"])
-    rep = tl.judge(argparse.Namespace(kappa=meta["kappa"]), model, [200], 10.0)
+    rep = tl.evaluate(argparse.Namespace(kappa=meta["kappa"]), model, [200], 10.0)
     e = rep["h_rms_error_m"]
     say("  h rms", e)
     assert e["learned"] * 2 < e["r1"]
