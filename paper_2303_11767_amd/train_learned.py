@@ -245,6 +245,16 @@ def evaluate(args, model, seeds, t_eval, dtype="f64"):
 KAPPAS = (1.0, 2.0, 4.0, 8.0, 16.0, 1.0e30)
 
 
+def pick_kappa(errs, tol=0.05):
+    """The smallest trust bound whose error is within tol of the best one
+    (errs: kappa -> validation error); non-finite errors never qualify."""
+    finite = {k: e for k, e in errs.items() if math.isfinite(e)}
+    if not finite:
+        raise ValueError("no finite validation error")
+    best = min(finite.values())
+    return min(k for k, e in finite.items() if e <= (1.0 + tol) * best)
+
+
 def select_kappa(args):
     """The trust bound is a tuning choice of the fallback, so it is chosen on
     validation seeds (disjoint from the training seeds 0.. and the held-out
@@ -257,8 +267,7 @@ def select_kappa(args):
         rep = evaluate(argparse.Namespace(kappa=k), model, seeds, args.t_eval)
         errs[k] = rep["h_rms_error_m"]["learned"]
         log(f"kappa {k:g}: learned {errs[k]:.4e} m (plain r1 {rep['h_rms_error_m']['r1']:.4e} m)")
-    best = min(errs.values())
-    chosen = min(k for k, e in errs.items() if e <= 1.05 * best)
+    chosen = pick_kappa(errs)
     meta["kappa"] = chosen
     meta["kappa_selection"] = {"seeds": list(seeds), "t_eval_s": args.t_eval,
                                "learned_h_rms_m": {f"{k:g}": e for k, e in errs.items()}}
