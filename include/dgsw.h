@@ -268,6 +268,12 @@ int dg_ens_autotune(dg_ens *ens, const void *q, void *work, const char *cache_pa
  * HIP graphs of whole step sequences (launch cost paid once per replay).
  * The pointers and step sizes are baked in at capture (an ensemble's dt is
  * read from its device table at run time, so dg_ens_set_dt still applies).
+ * A graph pins the context or ensemble it was captured on: dg_free /
+ * dg_ens_free called while graphs of it are live return DG_OK but defer the
+ * release of its device tables to the last dg_graph_free, and
+ * dg_ens_set_schedule / dg_ens_autotune return DG_EINVAL while graphs of
+ * the ensemble are live (the schedule is baked into them).  Capturing on an
+ * object whose free was deferred returns DG_EINVAL.
  * ------------------------------------------------------------------------- */
 typedef struct dg_graph dg_graph;
 int dg_graph_rk(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme,
@@ -330,13 +336,13 @@ typedef struct {
   double kappa;             /* trust bound, >= 0                                   */
 } dg_learned;
 int dg_learned_workspace_size(const dg_ctx *ctx, int64_t *bytes);
-/* dqdt = L1(q) + c(q).  fallbacks: optional device int32 incremented by the
+/* dqdt = L1(q) + c(q).  fallbacks: optional device int64 incremented by the
  * number of elements that fell back. */
 int dg_rhs_learned(dg_ctx *ctx, const dg_learned *net, const void *q, void *dqdt,
-                   void *workspace, int32_t *fallbacks, void *hip_stream);
+                   void *workspace, int64_t *fallbacks, void *hip_stream);
 /* nsteps SSP-RK3 steps with the learned right-hand side (work: 2 states). */
 int dg_rk_step_learned(dg_ctx *ctx, const dg_learned *net, void *q, void *work,
-                       void *workspace, double dt, int32_t nsteps, int32_t *fallbacks,
+                       void *workspace, double dt, int32_t nsteps, int64_t *fallbacks,
                        void *hip_stream);
 
 /* ---- Planar linear advection (section 4.1's convergence test, equation

@@ -218,7 +218,7 @@ class Mesh:
         check(self._lib.dg_graph_rk(self._ctx, self._ptr(q, "q"),
                                     self._ptr(work, "work", self.work_size(scheme)), float(dt),
                                     int(scheme), int(nsteps), ctypes.byref(g)))
-        return Graph(self._lib, g, (q, work))
+        return Graph(self._lib, g, (q, work, self))
 
     def close(self):
         if getattr(self, "_ctx", None) and getattr(self, "_owns", False):
@@ -420,7 +420,7 @@ class Ensemble:
         check(self._lib.dg_graph_ens(self._e, self._ptr(q, "q", self.size),
                                      self._ptr(work, "work", 2 * self.size), int(nsteps),
                                      ctypes.byref(g)))
-        return Graph(self._lib, g, (q, work))
+        return Graph(self._lib, g, (q, work, self))
 
     def close(self):
         for m in getattr(self, "members", []):

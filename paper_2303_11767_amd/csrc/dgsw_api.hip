@@ -310,6 +310,13 @@ int dg_get_levels(const dg_ctx *ctx, int32_t *n_levels) {
 }
 
 int dg_free(dg_ctx *ctx) {
+  if (!ctx) return DG_OK;
+  // a captured graph reads the context's device tables: keep them until the
+  // last such graph is freed (dg_graph_free completes the release)
+  if (ctx->graphs > 0) {
+    ctx->freed = 1;
+    return DG_OK;
+  }
   release(ctx);
   return DG_OK;
 }

@@ -27,6 +27,8 @@ struct dg_ctx {
   int levels = 1;              // identical layers held by every state buffer
   int64_t level_n = 0;         // values of one layer, E * 3 * N
   int member = 0;              // 1: owned by an ensemble (one layer only)
+  int graphs = 0;              // live dg_graph objects captured on this context
+  int freed = 0;               // dg_free called while graphs were live: release deferred
 };
 
 namespace dgsw {

@@ -34,11 +34,18 @@ struct dg_ens {
   // members of one order form one contiguous group of the sorted work list
   struct Group { int np, begin, end, parts, bounds_off; double cost; };
   std::vector<Group> groups;
+  int graphs = 0;   // live dg_graph objects captured on this ensemble
+  int freed = 0;    // dg_ens_free called while graphs were live: release deferred
 };
 
+// A captured graph holds the device addresses of its context's or ensemble's
+// tables and schedule, so it pins that object: frees are deferred until the
+// last graph is gone, and the ensemble schedule cannot change meanwhile.
 struct dg_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  dg_ctx *ctx = nullptr;
+  dg_ens *ens = nullptr;
 };
 
 namespace {
@@ -255,6 +262,10 @@ int dg_ens_init(const dg_mesh_desc *members, int32_t n_members, void *hip_stream
 }
 
 int dg_ens_free(dg_ens *ens) {
+  if (ens && ens->graphs > 0) {
+    ens->freed = 1;
+    return DG_OK;
+  }
   ens_release(ens);
   return DG_OK;
 }
@@ -335,6 +346,8 @@ int dg_ens_set_schedule(dg_ens *ens, int32_t waves_per_group, int32_t groups, in
     return fail(DG_EINVAL, "waves_per_group must be 1, 2 or 4");
   if (groups < 0 || groups > (1 << 20)) return fail(DG_EINVAL, "groups out of range");
   if (fused != 0 && fused != 1) return fail(DG_EINVAL, "fused must be 0 or 1");
+  if (ens->graphs > 0)
+    return fail(DG_EINVAL, "the schedule is baked into live graphs of this ensemble: free them first");
   return upload_schedule(ens, waves_per_group, groups, fused);
 }
 
@@ -349,6 +362,8 @@ int dg_ens_get_schedule(const dg_ens *ens, int32_t *waves_per_group, int32_t *gr
 
 int dg_ens_autotune(dg_ens *ens, const void *q, void *work, const char *cache_path, void *hip_stream) {
   if (!ens || !q || !work) return fail(DG_EINVAL, "NULL argument");
+  if (ens->graphs > 0)
+    return fail(DG_EINVAL, "the schedule is baked into live graphs of this ensemble: free them first");
   const std::string key = ens_key(ens);
   if (cache_path) {
     std::ifstream in(cache_path);
@@ -416,12 +431,24 @@ static int capture(dg_graph **out, const std::function<int(hipStream_t)> &body);
 int dg_graph_rk(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme, int32_t nsteps,
                 dg_graph **out) {
   if (!ctx || !out) return fail(DG_EINVAL, "NULL argument");
-  return capture(out, [&](hipStream_t s) { return dg_rk_step(ctx, q, work, dt, scheme, nsteps, s); });
+  if (ctx->freed) return fail(DG_EINVAL, "context already freed");
+  const int rc = capture(out, [&](hipStream_t s) { return dg_rk_step(ctx, q, work, dt, scheme, nsteps, s); });
+  if (rc == DG_OK) {
+    (*out)->ctx = ctx;
+    ++ctx->graphs;
+  }
+  return rc;
 }
 
 int dg_graph_ens(dg_ens *ens, void *q, void *work, int32_t nsteps, dg_graph **out) {
   if (!ens || !out) return fail(DG_EINVAL, "NULL argument");
-  return capture(out, [&](hipStream_t s) { return dg_ens_rk_step(ens, q, work, nsteps, s); });
+  if (ens->freed) return fail(DG_EINVAL, "ensemble already freed");
+  const int rc = capture(out, [&](hipStream_t s) { return dg_ens_rk_step(ens, q, work, nsteps, s); });
+  if (rc == DG_OK) {
+    (*out)->ens = ens;
+    ++ens->graphs;
+  }
+  return rc;
 }
 
 int dg_graph_launch(dg_graph *graph, void *hip_stream) {
@@ -435,6 +462,8 @@ int dg_graph_free(dg_graph *graph) {
   if (!graph) return DG_OK;
   if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
   if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  if (graph->ctx && --graph->ctx->graphs == 0 && graph->ctx->freed) dg_free(graph->ctx);
+  if (graph->ens && --graph->ens->graphs == 0 && graph->ens->freed) dg_ens_free(graph->ens);
   delete graph;
   return DG_OK;
 }

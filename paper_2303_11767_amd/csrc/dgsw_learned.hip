@@ -282,7 +282,7 @@ int dg_learned_workspace_size(const dg_ctx *ctx, int64_t *bytes) {
 namespace {
 
 int learned_stage(dg_ctx *ctx, const dg_learned *net, const LearnWs &t, const void *q, const void *q0, void *out,
-                  int combine, double c0, double c1, double dt, int32_t *fallbacks, hipStream_t s) {
+                  int combine, double c0, double c1, double dt, int64_t *fallbacks, hipStream_t s) {
   const int dt_ = ctx->d.dtype == DG_F64 ? 0 : 1;
   // plain r = 1 right-hand side into the workspace
   dgsw::StageLaunch a;
@@ -328,7 +328,7 @@ int check_learned(const dg_ctx *ctx, const dg_learned *net, const void *workspac
 extern "C" {
 
 int dg_rhs_learned(dg_ctx *ctx, const dg_learned *net, const void *q, void *dqdt, void *workspace,
-                   int32_t *fallbacks, void *hip_stream) {
+                   int64_t *fallbacks, void *hip_stream) {
   int rc = check_learned(ctx, net, workspace);
   if (rc != DG_OK) return rc;
   if (!q || !dqdt) return fail(DG_EINVAL, "NULL argument");
@@ -340,7 +340,7 @@ int dg_rhs_learned(dg_ctx *ctx, const dg_learned *net, const void *q, void *dqdt
 }
 
 int dg_rk_step_learned(dg_ctx *ctx, const dg_learned *net, void *q, void *work, void *workspace, double dt,
-                       int32_t nsteps, int32_t *fallbacks, void *hip_stream) {
+                       int32_t nsteps, int64_t *fallbacks, void *hip_stream) {
   int rc = check_learned(ctx, net, workspace);
   if (rc != DG_OK) return rc;
   if (!q || !work) return fail(DG_EINVAL, "NULL argument");

@@ -159,7 +159,7 @@ struct MlpCorrection {           // the learned stage's correction step (FROM_Q)
   float kappa;
   float *C;
   double *partial;
-  int *fallback;
+  int64_t *fallback;
 };
 constexpr int kWaves = 8;                 // wavefronts per workgroup
 constexpr int kLd = kHidden + 8;          // LDS row stride in BF16 (+16 B: no bank conflicts)
@@ -332,7 +332,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_fused(const T *__restrict__
         for (int k = 0; k < 12; ++k) cor.C[(size_t)e * 12 + k] = c[k];
       }
       const unsigned long long fb = __ballot(fell);
-      if (cor.fallback && lane == 0 && fb != 0ull) atomicAdd(cor.fallback, (int)__popcll(fb));
+      if (cor.fallback && lane == 0 && fb != 0ull)
+        atomicAdd(reinterpret_cast<unsigned long long *>(cor.fallback), (unsigned long long)__popcll(fb));
       // fixed-order (tree) wavefront sum of the 64 rows' masses
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) mass += __shfl_down(mass, off, 64);
@@ -600,7 +601,7 @@ hipError_t launch_features(int dtype, const void *q, int n_lon, int n_lat, const
 // delta = -(sum of partials) / (sum over elements of mass_w[j][0]): the mode-00
 // h-correction that makes the total h-mass change of the correction zero.
 // Every block of the output kernel forms it itself, in the same fixed order.
-__device__ __forceinline__ float block_mass_delta(const double *__restrict__ partial, int nparts, double area,
+__device__ __forceinline__ double block_mass_delta(const double *__restrict__ partial, int nparts, double area,
                                                   double *sh) {
   double acc = 0.0;
   for (int k = threadIdx.x; k < nparts; k += 256) acc += partial[k];
@@ -610,7 +611,7 @@ __device__ __forceinline__ float block_mass_delta(const double *__restrict__ par
     if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
     __syncthreads();
   }
-  return (float)(-sh[0] / area);
+  return -sh[0] / area;
 }
 
 // out = combine ? c0 q0 + c1 (q + dt (L1 + c)) : L1 + c, with c_(h,00) = delta;
@@ -622,7 +623,7 @@ __global__ __launch_bounds__(256) void k_learned_out(const T *__restrict__ q, co
                                                      int nparts, double area, int E, int combine, T c0, T ce, T dt,
                                                      T *out) {
   __shared__ double sh[256];
-  const float delta = block_mass_delta(partial, nparts, area, sh);
+  const double delta = block_mass_delta(partial, nparts, area, sh);
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= E * 12) return;
   const int k = idx % 12;

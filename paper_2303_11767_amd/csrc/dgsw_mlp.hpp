@@ -31,7 +31,7 @@ struct CorrectionArgs {
   float kappa;
   float *C;                      // corrections [E][12]
   double *partial;               // one h-mass per workgroup: mlp_fused_blocks(E)
-  int *fallback;                 // optional device counter
+  int64_t *fallback;             // optional device counter (64-bit: never wraps)
 };
 inline int mlp_fused_blocks(int rows) { return (rows + 63) / 64; }
 // Whole-network inference, 64 rows per workgroup, activations in LDS.  With q:

@@ -111,7 +111,7 @@ class LearnedRHS:
         b = ctypes.c_int64()
         check(load().dg_learned_workspace_size(mesh._ctx, ctypes.byref(b)))
         self.workspace = torch.empty(b.value, dtype=torch.uint8, device=params.device)
-        self.fallbacks = torch.zeros(1, dtype=torch.int32, device=params.device)
+        self.fallbacks = torch.zeros(1, dtype=torch.int64, device=params.device)
 
     def rhs(self, q, out=None, stream=None):
         if out is None:

@@ -5,10 +5,11 @@ f = dF/dlam + dG/dtheta - S of U* (its modal weak projection set with
 dg_set_forcing); the GPU then runs SSP-RK3 from the projection of U* for one
 simulated hour, and the cos-weighted L2 error of h against the projection
 of U* is measured on three meshes per order.  The paper's convergence
-tables report order about r + 1 for smooth solutions; the operator's
-consistency guarantees at least order r, which is what the test asserts
-(with margin); the measured rates are printed.  Forcing and projections
-come from the oracle (inputs only); the run is the library's."""
+tables report order about r + 1 for smooth solutions (2.00 / 3.00 /
+3.96-4.00 for p = 1, 2, 3); the test asserts the finest-pair rate within
+0.3 of r + 1 for r = 1..5 (r = 5: the order of the 360 x 180 FP32
+workload).  Forcing and projections come from the oracle (inputs only); the
+run is the library's."""
 import sys
 
 import numpy as np
@@ -75,7 +76,7 @@ def _h_error(m, q, ref):
     return np.sqrt(e2 / n2)
 
 
-@pytest.mark.parametrize("order", [1, 2, 3, 4])
+@pytest.mark.parametrize("order", [1, 2, 3, 4, 5])
 def test_manufactured_steady_state_converges(dg, order):
     errs = []
     for n_lat in (8, 16, 32):
@@ -98,4 +99,4 @@ def test_manufactured_steady_state_converges(dg, order):
     rates = np.log2(errs[:-1] / errs[1:])
     say("  rates", rates)
     assert np.all(np.isfinite(errs))
-    assert rates[-1] > order - 0.5, (errs, rates)
+    assert abs(rates[-1] - (order + 1)) < 0.3, (errs, rates)

@@ -155,6 +155,59 @@ def test_graph_replays_match_eager(dg):
     gm.close()
 
 
+def test_graph_pins_schedule_and_owner(dg):
+    """A live graph bakes in the ensemble's schedule and tables: changing the
+    schedule or autotuning is refused while it lives, and freeing the
+    ensemble (or a mesh) under a live graph defers the release, so the graph
+    still replays correctly; after the graph is freed the schedule can
+    change again."""
+    say("graph pins schedule and owner")
+    ens, q, dts = build(dg, "f32")
+    work = ens.empty_work()
+    qe, we = q.clone(), ens.empty_work()
+    ens.rk_step(qe, we, nsteps=2)
+    qg = q.clone()
+    g = ens.graph(qg, work, nsteps=2)
+    with pytest.raises(dg.DGError) as ei:
+        ens.set_schedule(2, 64, 0)
+    assert ei.value.code == -1
+    with pytest.raises(dg.DGError):
+        ens.autotune(q, ens.empty_work())
+    g.close()
+    ens.set_schedule(2, 64, 0)                       # no live graph: allowed again
+    # free under a live graph: the C release is deferred to dg_graph_free
+    lib = ens._lib
+    import ctypes
+    gh = ctypes.c_void_p()
+    qg2 = q.clone()
+    assert lib.dg_graph_ens(ens._e, ctypes.c_void_p(qg2.data_ptr()), ctypes.c_void_p(work.data_ptr()),
+                            2, ctypes.byref(gh)) == 0
+    for m in ens.members:
+        m._ctx = None
+    assert lib.dg_ens_free(ens._e) == 0
+    ens._e = None
+    assert lib.dg_graph_launch(gh, None) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(qg2, qe)
+    assert lib.dg_graph_free(gh) == 0
+    # the same for a single mesh
+    mesh = dg.Mesh(24, 12, 2, dtype="f64")
+    qm, _ = band_limited_state(24, 12, 2, 4, 77)
+    qa = torch.from_numpy(qm).cuda()
+    qb = qa.clone()
+    mesh.rk_step(qb, mesh.empty_work(), 10.0, nsteps=3)
+    wm = mesh.empty_work()
+    gm = ctypes.c_void_p()
+    assert lib.dg_graph_rk(mesh._ctx, ctypes.c_void_p(qa.data_ptr()), ctypes.c_void_p(wm.data_ptr()),
+                           10.0, 3, 3, ctypes.byref(gm)) == 0
+    assert lib.dg_free(mesh._ctx) == 0
+    mesh._ctx = None
+    assert lib.dg_graph_launch(gm, None) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(qa, qb)
+    assert lib.dg_graph_free(gm) == 0
+
+
 def test_full_ensemble_sampled_members_vs_oracle(dg):
     """The 64-member FP32 ensemble of the benchmark (orders 2-4, 90x45 ..
     360x180) in its autotuned launch configuration: three members (the first,

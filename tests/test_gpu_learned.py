@@ -209,11 +209,17 @@ def test_learned_rhs_fallback_and_mass(dg):
     assert net3.fallbacks.item() == 0
     diff = (out3 - mesh3.rhs(q3)).abs().max().item()
     assert diff > 0
-    m_plain = mesh3.mass(mesh3.rhs(q3))[0]
+    plain3 = mesh3.rhs(q3)
+    m_plain = mesh3.mass(plain3)[0]
     m_learn = mesh3.mass(out3)[0]
-    scale = mesh3.mass(q3)[0] / 3600.0
-    say("  h-mass tendency plain", m_plain, "learned", m_learn, "scale", scale)
-    assert abs(m_learn - m_plain) <= 1e-9 * scale
+    # the correction's own h-mass, element by element in absolute value: the
+    # scale of the roundoff left after the global (h, mode 00) fix (FP64)
+    o = SphereDG(mesh3.n_lon, mesh3.n_lat, 1)
+    d = o.grid((out3 - plain3).cpu().numpy())[:, :, 0]               # [j, i, 4]
+    m_abs = o.R ** 2 * 2.0 * np.abs(np.einsum("jn,jin->ji", o.M[:, 0, :], d)).sum()
+    say("  h-mass tendency plain", m_plain, "learned", m_learn, "correction |mass|", m_abs)
+    assert m_abs > 0
+    assert abs(m_learn - m_plain) <= 1e-13 * m_abs + 1e-13 * abs(m_plain)
 
 
 def test_learned_rhs_matches_oracle(dg):

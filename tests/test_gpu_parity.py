@@ -13,7 +13,7 @@ import pytest
 
 from dg_inputs import band_limited_state, lake_at_rest_state
 from oracle import SphereDG, butcher_step, ssp_rk3
-from parity_util import TOL, errors
+from parity_util import TOL, errors, norm_bound, ulp_sensitivity
 
 pytestmark = pytest.mark.gpu
 
@@ -47,22 +47,33 @@ def oracle_input(q, dtype):
     return q.astype(np.float32).astype(np.float64) if dtype == "f32" else q
 
 
-def check_rhs(dg, n_lon, n_lat, order, dtype, L, seed, kernel=None, **kw):
-    say("rhs", n_lon, n_lat, order, dtype, L, seed, kernel, kw)
+def check_rhs(dg, n_lon, n_lat, order, dtype, L, seed, kernel=None, kernels=None, **kw):
+    """The GPU right-hand side against the oracle on the band-limited state:
+    componentwise bar, and the normwise error bounded by NORM_K times the
+    oracle's one-ulp sensitivity (both printed).  kernels: several layouts
+    checked against one oracle evaluation."""
+    say("rhs", n_lon, n_lat, order, dtype, L, seed, kernel or kernels, kw)
     q, _ = band_limited_state(n_lon, n_lat, order, L, seed)
     qin = oracle_input(q, dtype)
     okw = {k: v for k, v in kw.items() if k in ("metric", "alpha_mode", "alpha")}
     m = SphereDG(n_lon, n_lat, order, **okw)
     ref, sc = m.rhs(qin), m.rhs_scale(qin)
+    sens = ulp_sensitivity(m.rhs, qin, ref, dtype, seed=seed)
     mesh = make(dg, n_lon, n_lat, order, dtype, **kw)
-    if kernel:
-        mesh.kernel = kernel
-    got = mesh.rhs(to_dev(q, dtype)).cpu().numpy()
-    comp, norm = errors(got, ref, sc)
-    say("  componentwise", comp, "normwise", norm)
-    assert np.all(np.isfinite(got))
-    assert np.all(comp <= TOL[dtype]), (comp, norm)
-    return comp, norm
+    qd = to_dev(q, dtype)
+    out = []
+    for kern in (kernels or [kernel]):
+        if kern:
+            mesh.kernel = kern
+        got = mesh.rhs(qd).cpu().numpy()
+        comp, norm = errors(got, ref, sc)
+        say("  kernel", mesh.kernel, "componentwise", comp, "normwise", norm,
+            "one-ulp sensitivity", sens, "normwise/sensitivity", norm / sens)
+        assert np.all(np.isfinite(got))
+        assert np.all(comp <= TOL[dtype]), (comp, norm)
+        assert np.all(norm <= norm_bound(sens, dtype)), (norm, sens)
+        out.append((comp, norm))
+    return out[0] if len(out) == 1 else out
 
 
 # ---------------------------------------------------------------- right-hand side
@@ -97,6 +108,14 @@ def test_rhs_c2(dg, dtype, kernel):
 def test_rhs_c3(dg, dtype, kernel):
     """r = 5, 360 x 180, l <= 32."""
     check_rhs(dg, 360, 180, 5, dtype, L=32, seed=3, kernel=kernel)
+
+
+@pytest.mark.timeout(600)
+def test_rhs_large_mesh_f64(dg):
+    """r = 3, 1440 x 720, FP64, l <= 32 (the mesh whose 398 MB state does not
+    fit the Infinity Cache; the bandwidth measurement's workload): the whole
+    right-hand side against the oracle, both layouts."""
+    check_rhs(dg, 1440, 720, 3, "f64", L=32, seed=5, kernels=["half", "line"])
 
 
 @pytest.mark.parametrize("dims", [(90, 45, 2, "f32"), (180, 90, 3, "f64")])

@@ -13,7 +13,7 @@ import pytest
 
 from dg_inputs import gaussian_bump_plane, random_plane_state
 from oracle import PlaneDG, butcher_step
-from parity_util import TOL, errors
+from parity_util import TOL, errors, norm_bound, ulp_sensitivity
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -56,13 +56,15 @@ def check_rhs(dg, nx, ny, order, dtype, seed, kernel="line", **kw):
     okw = {k: v for k, v in kw.items() if k in ("alpha_mode", "alpha")}
     m = PlaneDG(nx, ny, order, LX, LY, gravity=G, f=F, **okw)
     ref, sc = m.rhs(qin), m.rhs_scale(qin)
+    sens = ulp_sensitivity(m.rhs, qin, ref, dtype, seed=seed)
     mesh = plane(dg, nx, ny, order, dtype, **kw)
     mesh.kernel = kernel
     got = mesh.rhs(to_dev(q, dtype)).cpu().numpy()
     comp, norm = errors(got, ref, sc)
-    say("  componentwise", comp, "normwise", norm)
+    say("  componentwise", comp, "normwise", norm, "one-ulp sensitivity", sens)
     assert np.all(np.isfinite(got))
     assert np.all(comp <= TOL[dtype]), (comp, norm)
+    assert np.all(norm <= norm_bound(sens, dtype)), (norm, sens)
 
 
 @pytest.mark.parametrize("kernel", ["line", "half"])

@@ -136,10 +136,11 @@ def test_mass_longitude_blocks_and_dblquad():
 
 
 # ---------------------------------------------------------------- r = 0 is first-order finite volume
-def _fv_rhs(Q, n_lon, n_lat, balanced=True):
+def _fv_rhs(Q, n_lon, n_lat, balanced=True, alpha=None):
     """Textbook first-order finite volume on the lat-lon grid with the local
     Lax-Friedrichs flux, written for cell values Q[j, i, v]:
-    dlam (sin t - sin b) dQ/dt = -dth (F_E - F_W) - dlam (G_N - G_S) + dlam dth S(centre)."""
+    dlam (sin t - sin b) dQ/dt = -dth (F_E - F_W) - dlam (G_N - G_S) + dlam dth S(centre).
+    alpha given: the global Lax-Friedrichs flux, one fixed speed at every face."""
     dl, dt_ = 2 * np.pi / n_lon, np.pi / n_lat
     out = np.zeros_like(Q)
     for j in range(n_lat):
@@ -159,10 +160,12 @@ def _fv_rhs(Q, n_lon, n_lat, balanced=True):
 
             def llf_lam(ql, qr):
                 a = max(abs(ql[1] / ql[0]) + np.sqrt(G * ql[0]), abs(qr[1] / qr[0]) + np.sqrt(G * qr[0]))
+                a = a if alpha is None else alpha
                 return 0.5 * (fl(ql) + fl(qr)) - 0.5 * a / R * (qr - ql)
 
             def llf_th(qs, qn, c):
                 a = max(abs(qs[2] / qs[0]) + np.sqrt(G * qs[0]), abs(qn[2] / qn[0]) + np.sqrt(G * qn[0]))
+                a = a if alpha is None else alpha
                 return 0.5 * (gl(qs, c) + gl(qn, c)) - 0.5 * a * c / R * (qn - qs)
 
             q = Q[j, i]
@@ -195,13 +198,38 @@ def test_r0_equals_first_order_finite_volume(metric):
     assert np.all(np.abs(got - ref).max(axis=(0, 1)) <= 1e-13 * scale), (np.abs(got - ref).max(axis=(0, 1)), scale)
 
 
+@pytest.mark.parametrize("alpha", [150.0, 420.0])
+def test_r0_global_alpha_equals_global_lax_friedrichs(alpha):
+    """The fixed-speed ("global") branch of the Rusanov flux: at r = 0 the
+    method is first-order finite volume with the global Lax-Friedrichs flux,
+    F^ = (F- + F+)/2 - (alpha/2R)(q+ - q-) on longitude faces and
+    (alpha cos/2R)(q+ - q-) on latitude faces.  Two speeds, one below the
+    local wave speed (~330 m/s) and one above, so the dissipation term is
+    pinned with a coefficient that differs from the local one."""
+    n_lon, n_lat = 12, 7
+    rng = np.random.default_rng(12)
+    Q = np.empty((n_lat, n_lon, 3))
+    Q[..., 0] = 1e4 + 100 * rng.standard_normal((n_lat, n_lon))
+    Q[..., 1] = Q[..., 0] * 20 * rng.standard_normal((n_lat, n_lon))
+    Q[..., 2] = Q[..., 0] * 20 * rng.standard_normal((n_lat, n_lon))
+    m = SphereDG(n_lon, n_lat, 0, alpha_mode="global", alpha=alpha)
+    got = m.rhs((2.0 * Q).reshape(m.E, 3, 1)).reshape(n_lat, n_lon, 3) / 2.0
+    ref = _fv_rhs(Q, n_lon, n_lat, alpha=alpha)
+    scale = np.abs(ref).max(axis=(0, 1))
+    assert np.all(np.abs(got - ref).max(axis=(0, 1)) <= 1e-13 * scale), (np.abs(got - ref).max(axis=(0, 1)), scale)
+    # and it is not the local flux (the branch is taken)
+    loc = _fv_rhs(Q, n_lon, n_lat)
+    assert np.abs(loc - ref).max() > 1e-6 * np.abs(ref).max()
+
+
 # ---------------------------------------------------------------- weak form, literal per face
-def _weak_form_by_faces(q, n_lon, n_lat, order):
+def _weak_form_by_faces(q, n_lon, n_lat, order, alpha=None):
     """h(q) as the literal quadrature of equation "dg_parts" per element:
     volume term - sum over the four faces of (f* . n) phi, with the Rusanov
     flux written from each element's own side (own trace, opposite trace,
     outward normal), in physical (lambda, theta) coordinates, basis from
-    numpy's legval.  Pure Python loops: tiny meshes only."""
+    numpy's legval.  alpha given: a fixed speed in place of the local
+    eigenvalue estimate.  Pure Python loops: tiny meshes only."""
     n = order + 1
     xq, wq = npleg.leggauss(n)
     dl, dt_ = 2 * np.pi / n_lon, np.pi / n_lat
@@ -257,8 +285,9 @@ def _weak_form_by_faces(q, n_lon, n_lat, order):
                         opp = value(j, inb, -xs, xq[k])
                         th = lat(j, xq[k])
                         c = np.cos(th)
-                        a_ = max(abs(own[1] / own[0]) + np.sqrt(G * own[0]),
-                                 abs(opp[1] / opp[0]) + np.sqrt(G * opp[0])) / (R * c)
+                        spd = max(abs(own[1] / own[0]) + np.sqrt(G * own[0]),
+                                  abs(opp[1] / opp[0]) + np.sqrt(G * opp[0]))
+                        a_ = (spd if alpha is None else alpha) / (R * c)
                         Uo, Un = own * c, opp * c
                         fstar_n = 0.5 * (F(own) + F(opp)) * nrm[0] - 0.5 * a_ * (Un - Uo)
                         jac = dt_ / 2
@@ -271,8 +300,9 @@ def _weak_form_by_faces(q, n_lon, n_lat, order):
                         own = value(j, i, xq[k], ys)
                         opp = value(jn, i, xq[k], -ys)
                         c = np.cos(-np.pi / 2 + (j + (1 if name == "N" else 0)) * dt_)
-                        a_ = max(abs(own[2] / own[0]) + np.sqrt(G * own[0]),
-                                 abs(opp[2] / opp[0]) + np.sqrt(G * opp[0])) / R
+                        spd = max(abs(own[2] / own[0]) + np.sqrt(G * own[0]),
+                                  abs(opp[2] / opp[0]) + np.sqrt(G * opp[0]))
+                        a_ = (spd if alpha is None else alpha) / R
                         Uo, Un = own * c, opp * c
                         fstar_n = 0.5 * (Gf(own, c) + Gf(opp, c)) * nrm[1] - 0.5 * a_ * (Un - Uo)
                         jac = dl / 2
@@ -290,6 +320,19 @@ def test_residual_equals_literal_weak_form(order):
     m = SphereDG(n_lon, n_lat, order, metric="pointwise")
     got = m.residual(q)
     ref = _weak_form_by_faces(q, n_lon, n_lat, order)
+    scale = np.abs(ref).max(axis=(0, 1, 3))
+    err = np.abs(got - ref).max(axis=(0, 1, 3))
+    assert np.all(err <= 1e-12 * scale), (err, scale)
+
+
+def test_residual_global_alpha_equals_literal_weak_form():
+    """The global-speed Rusanov branch at r = 2 against the same literal
+    per-face quadrature with the fixed speed put into its flux."""
+    n_lon, n_lat, order, alpha = 5, 4, 2, 400.0
+    q, _ = band_limited_state(n_lon, n_lat, order, 3, seed=6)
+    m = SphereDG(n_lon, n_lat, order, metric="pointwise", alpha_mode="global", alpha=alpha)
+    got = m.residual(q)
+    ref = _weak_form_by_faces(q, n_lon, n_lat, order, alpha=alpha)
     scale = np.abs(ref).max(axis=(0, 1, 3))
     err = np.abs(got - ref).max(axis=(0, 1, 3))
     assert np.all(err <= 1e-12 * scale), (err, scale)
@@ -466,6 +509,44 @@ def test_operator_consistency_converges(order):
     rates = np.log2(errs[:-1] / errs[1:])
     assert np.all(errs[-1] < [0.05, 0.05, 0.02][order - 1]), errs
     assert np.all(rates[-1] > order - 0.75), rates
+
+
+def _h_l2_error(m, q, ref):
+    """Cos-weighted L2 norm of the h error, relative to that of ref (both
+    modal; the norm uses the mass matrix, which is exact)."""
+    d = m.grid(q - ref)[:, :, 0]
+    r = m.grid(ref)[:, :, 0]
+    return np.sqrt(np.einsum("jim,jmn,jin->", d, m.M, d) / np.einsum("jim,jmn,jin->", r, m.M, r))
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_manufactured_solution_time_integrated_rate(order):
+    """Convergence order r + 1 of the whole method in time (the rates of the
+    paper's section 4 convergence tables, 2.00 / 3.00 for p = 1, 2): the
+    smooth state U* is made steady by the forcing dF/dlam + dG/dtheta - S of
+    U*, the oracle runs SSP-RK3 from the projection of U* for one simulated
+    hour, and the cos-weighted L2 error of h decays like h^(r+1) between
+    16 x 8 and 32 x 16 elements.  The time step is CFL 0.2 against the
+    smallest element width (it shrinks like h^2, so the RK3 error is
+    negligible); a dropped or wrong term leaves an error that does not
+    converge, and a first-order flux or metric mistake lowers the rate."""
+    errs = []
+    cmax = 20.0 + np.sqrt(G * (H0 + 150.0)) + 10.0
+    for n_lat in (4, 8, 16):
+        m = SphereDG(2 * n_lat, n_lat, order)
+        q0 = m.project(_q_exact)
+        m.forcing = -m.weak_forcing(_dUdt)
+        dt = m.cfl_time_step(cmax, 0.2)
+        steps = int(np.ceil(3600.0 / dt))
+        q = q0.copy()
+        for _ in range(steps):
+            q = m.ssp_rk3_step(q, 3600.0 / steps)
+        errs.append(_h_l2_error(m, q, q0))
+    errs = np.array(errs)
+    rates = np.log2(errs[:-1] / errs[1:])
+    print("oracle mms", order, errs, rates)
+    assert abs(rates[-1] - (order + 1)) < 0.3, (errs, rates)
+    assert rates[0] > order, (errs, rates)
 
 
 # ---------------------------------------------------------------- time integration

@@ -29,10 +29,11 @@ def random_state(m, seed, h0=1000.0, dh=5.0, vel=2.0):
 
 
 # ---------------------------------------------------------------- r = 0 is first-order finite volume
-def _fv_rhs(Q, dx, dy):
+def _fv_rhs(Q, dx, dy, alpha=None):
     """First-order finite volume with the local Lax-Friedrichs flux on a
     doubly periodic grid of cell averages Q[j, i, v]:
-    dQ/dt = -(F_E - F_W)/dx - (G_N - G_S)/dy + (0, f hv, -f hu)."""
+    dQ/dt = -(F_E - F_W)/dx - (G_N - G_S)/dy + (0, f hv, -f hu).
+    alpha given: the global Lax-Friedrichs flux with that fixed speed."""
     ny, nx, _ = Q.shape
     out = np.zeros_like(Q)
 
@@ -46,6 +47,7 @@ def _fv_rhs(Q, dx, dy):
 
     def llf(ql, qr, fl, c):
         a = max(abs(ql[c] / ql[0]) + np.sqrt(G * ql[0]), abs(qr[c] / qr[0]) + np.sqrt(G * qr[0]))
+        a = a if alpha is None else alpha
         return 0.5 * (fl(ql) + fl(qr)) - 0.5 * a * (qr - ql)
 
     for j in range(ny):
@@ -72,6 +74,23 @@ def test_plane_r0_equals_first_order_finite_volume():
     ref = _fv_rhs(Q, LX / nx, LY / ny)
     scale = np.abs(ref).max(axis=(0, 1))
     assert np.all(np.abs(got - ref).max(axis=(0, 1)) <= 1e-13 * scale)
+
+
+def test_plane_r0_global_alpha_equals_global_lax_friedrichs():
+    """The fixed-speed Rusanov branch of the plane at r = 0: first-order
+    finite volume with the global Lax-Friedrichs flux."""
+    nx, ny, alpha = 9, 7, 130.0
+    rng = np.random.default_rng(4)
+    Q = np.empty((ny, nx, 3))
+    Q[..., 0] = 1000 + 5 * rng.standard_normal((ny, nx))
+    Q[..., 1] = Q[..., 0] * 2 * rng.standard_normal((ny, nx))
+    Q[..., 2] = Q[..., 0] * 2 * rng.standard_normal((ny, nx))
+    m = PlaneDG(nx, ny, 0, LX, LY, gravity=G, f=F, alpha_mode="global", alpha=alpha)
+    got = m.rhs((2.0 * Q).reshape(m.E, 3, 1)).reshape(ny, nx, 3) / 2.0
+    ref = _fv_rhs(Q, LX / nx, LY / ny, alpha=alpha)
+    scale = np.abs(ref).max(axis=(0, 1))
+    assert np.all(np.abs(got - ref).max(axis=(0, 1)) <= 1e-13 * scale)
+    assert np.abs(_fv_rhs(Q, LX / nx, LY / ny) - ref).max() > 1e-6 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("order", [0, 1, 2, 3, 5])
