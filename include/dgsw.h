@@ -302,17 +302,23 @@ int dg_mlp_workspace_size(int64_t rows, int64_t *bytes);
 int dg_mlp_forward(const float *params, const float *X, int64_t rows, float *Y, void *workspace,
                    void *hip_stream);
 /* Forward and backward pass of the mean squared error over the outputs with
- * mask[n] = 1 (mask: 12 device floats, 0 or 1) against T[rows][12]; rows a
- * multiple of 32.  grads (optional, device, param_count floats) receives the
- * gradient; loss (optional, device float) the mean squared error; with
- * lr > 0 one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with
- * the 1-based step) updates params, adam_m, adam_v in place.  Synchronises
- * hip_stream once (to read the mask). */
+ * mask[n] = 1 (mask: 12 HOST floats, each 0 or 1, read during the call, at
+ * least one 1; else DG_EINVAL) against T[rows][12]; rows a multiple of 32.
+ * grads (optional, device, param_count floats) receives the gradient; loss
+ * (optional, device float) the mean squared error; with lr > 0 one Adam step
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with the 1-based step)
+ * updates params, adam_m, adam_v in place.  Enqueues only: no
+ * synchronisation, so a training loop runs without host round trips. */
 int dg_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t step, float lr,
                       const float *X, const float *T, const float *mask, int64_t rows,
                       float *grads, float *loss, void *workspace, void *hip_stream);
-/* Cos-weighted L2 projection of a state of any order onto order 1 on the
- * same mesh (dst must have order 1, same mesh and dtype). */
+/* Cos-weighted L2 projection q_dst = M_k^-1 int q_src phi_k cos(theta) of a
+ * state onto the order-k basis of the same mesh, k = dst's order (the mass
+ * matrix of section 2; longitude degrees above k are dropped, latitude
+ * degrees mix per row).  For k >= the source order the state already lies
+ * in the target space and is copied into it (higher modes zero).  src and
+ * dst: same mesh (size, sphere or plane) and dtype, one layer; q_src and
+ * q_dst: different device buffers, else DG_EINVAL. */
 int dg_project(const dg_ctx *src, const dg_ctx *dst, const void *q_src, void *q_dst,
                void *hip_stream);
 /* Stencil features X[E][108] (FP32, device) of an order-1 state, standardised

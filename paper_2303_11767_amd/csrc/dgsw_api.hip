@@ -47,7 +47,7 @@ void release(dg_ctx *c) {
   if (c->d_mass_w) (void)hipFree(c->d_mass_w);
   if (c->d_partial) (void)hipFree(c->d_partial);
   if (c->d_out4) (void)hipFree(c->d_out4);
-  if (c->d_proj1) (void)hipFree(c->d_proj1);
+  if (c->d_proj) (void)hipFree(c->d_proj);
   delete c;
 }
 
@@ -126,23 +126,43 @@ int make_ctx(const dg_mesh_desc *desc, const dgsw::HostTables &t, hipStream_t s,
                   desc->alpha_mode == DG_ALPHA_GLOBAL ? desc->alpha : 0.0, hg.data());
   dgsw::fill_rows(dt, c->np, t, hr.data());
 
-  // projection onto order 1 on the same mesh: P_j = M1_j^-1 Mth_j[0..1][:],
-  // M1_j the leading 2 x 2 block of the latitude mass matrix (orders 0, 1)
+  // cos-weighted projection onto every order k = 0..7 on the same mesh, per
+  // latitude row j: P_kj = Mk_j^-1 Mth_j[0..k][:], Mk_j the leading (k+1)^2
+  // block of the latitude mass matrix (k <= r); for k > r the state already
+  // lies in the target space and the rows are the identity (embedding)
   const int npp = c->np;
-  std::vector<double> proj((size_t)desc->n_lat * 2 * npp, 0.0);
+  std::vector<double> proj((size_t)desc->n_lat * npp * dgsw::proj_rows_total(), 0.0);
   for (int j = 0; j < desc->n_lat; ++j) {
     const double *Mj = &t.Mth[(size_t)j * npp * npp];
     c->mass_area += desc->n_lon * t.mass_w[(size_t)j * npp + 0];
-    if (npp == 1) {
-      proj[(size_t)j * 2 * npp + 0] = 1.0;   // order 0: the constant maps to mode 00
-      continue;
+    for (int k = 0; k <= dgsw::kMaxOrder; ++k) {
+      const int nk = k + 1;
+      double *Pk = &proj[dgsw::proj_offset(k, desc->n_lat, npp) + (size_t)j * nk * npp];
+      if (k >= npp - 1) {
+        for (int b = 0; b < npp; ++b) Pk[b * npp + b] = 1.0;
+        continue;
+      }
+      // Gauss-Jordan on [Mk | Mth rows 0..k]: the left block is symmetric
+      // positive definite (a Gram matrix), so no pivoting is needed
+      double A[dgsw::kMaxNP][dgsw::kMaxNP], X[dgsw::kMaxNP][dgsw::kMaxNP];
+      for (int r = 0; r < nk; ++r)
+        for (int cc = 0; cc < nk; ++cc) A[r][cc] = Mj[r * npp + cc];
+      for (int r = 0; r < nk; ++r)
+        for (int b = 0; b < npp; ++b) X[r][b] = Mj[r * npp + b];
+      for (int piv = 0; piv < nk; ++piv) {
+        const double d = 1.0 / A[piv][piv];
+        for (int cc = 0; cc < nk; ++cc) A[piv][cc] *= d;
+        for (int b = 0; b < npp; ++b) X[piv][b] *= d;
+        for (int r = 0; r < nk; ++r) {
+          if (r == piv) continue;
+          const double f = A[r][piv];
+          for (int cc = 0; cc < nk; ++cc) A[r][cc] -= f * A[piv][cc];
+          for (int b = 0; b < npp; ++b) X[r][b] -= f * X[piv][b];
+        }
+      }
+      for (int r = 0; r < nk; ++r)
+        for (int b = 0; b < npp; ++b) Pk[r * npp + b] = X[r][b];
     }
-    const double a = Mj[0], b = Mj[1], cc = Mj[npp], d = Mj[npp + 1];
-    const double det = a * d - b * cc;
-    const double inv[4] = {d / det, -b / det, -cc / det, a / det};
-    for (int r = 0; r < 2; ++r)
-      for (int bb = 0; bb < npp; ++bb)
-        proj[((size_t)j * 2 + r) * npp + bb] = inv[r * 2 + 0] * Mj[0 * npp + bb] + inv[r * 2 + 1] * Mj[1 * npp + bb];
   }
 
   hipError_t e;
@@ -151,7 +171,7 @@ int make_ctx(const dg_mesh_desc *desc, const dgsw::HostTables &t, hipStream_t s,
       (e = hipMalloc(reinterpret_cast<void **>(&c->d_mass_w), t.mass_w.size() * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(reinterpret_cast<void **>(&c->d_partial), dgsw::mass_blocks() * 4 * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(reinterpret_cast<void **>(&c->d_out4), 4 * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(reinterpret_cast<void **>(&c->d_proj1), proj.size() * sizeof(double))) != hipSuccess) {
+      (e = hipMalloc(reinterpret_cast<void **>(&c->d_proj), proj.size() * sizeof(double))) != hipSuccess) {
     release(c);
     return fail(DG_ENOMEM, std::string("hipMalloc of context tables: ") + hipGetErrorString(e));
   }
@@ -159,7 +179,7 @@ int make_ctx(const dg_mesh_desc *desc, const dgsw::HostTables &t, hipStream_t s,
       (e = hipMemcpyAsync(c->d_rows, hr.data(), rb, hipMemcpyHostToDevice, s)) != hipSuccess ||
       (e = hipMemcpyAsync(c->d_mass_w, t.mass_w.data(), t.mass_w.size() * sizeof(double),
                           hipMemcpyHostToDevice, s)) != hipSuccess ||
-      (e = hipMemcpyAsync(c->d_proj1, proj.data(), proj.size() * sizeof(double), hipMemcpyHostToDevice,
+      (e = hipMemcpyAsync(c->d_proj, proj.data(), proj.size() * sizeof(double), hipMemcpyHostToDevice,
                           s)) != hipSuccess ||
       (e = hipStreamSynchronize(s)) != hipSuccess) {
     release(c);
@@ -419,22 +439,14 @@ int dg_rhs(dg_ctx *ctx, const void *q, void *dqdt, void *hip_stream) {
   return stage(ctx, q, nullptr, dqdt, 0, 0.0, 1.0, 0.0, static_cast<hipStream_t>(hip_stream));
 }
 
-int dg_rk_step(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme, int32_t nsteps,
-               void *hip_stream) {
-  if (!ctx || !q || !work) return fail(DG_EINVAL, "NULL argument");
-  if (!aligned16(q) || !aligned16(work)) return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
-  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
-  if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
-  int64_t wn = 0;
-  int rc = dg_work_size(ctx, scheme, &wn);
-  if (rc != DG_OK) return rc;
+}  // extern "C"
+
+// nsteps steps of the scheme on q with the stage states in work (already
+// checked: dg_work_size values, not overlapping q); shared by dg_rk_step.
+static int rk_steps(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme, int32_t nsteps,
+                    hipStream_t s) {
+  int rc = DG_OK;
   const size_t bytes = ctx->state_n * ctx->elem_bytes;
-  {
-    const char *a = static_cast<const char *>(q);
-    const char *b = static_cast<const char *>(work);
-    if (a < b + wn * ctx->elem_bytes && b < a + bytes) return fail(DG_EINVAL, "q and work overlap");
-  }
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
   char *w0 = static_cast<char *>(work);
   char *w1 = w0 + bytes;
   for (int n = 0; n < nsteps; ++n) {
@@ -473,6 +485,34 @@ int dg_rk_step(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme, int3
     }
   }
   return DG_OK;
+}
+
+// Argument checks of an RK step on q; wn receives the work values the scheme needs.
+static int rk_check(dg_ctx *ctx, const void *q, double dt, int32_t scheme, int32_t nsteps,
+                    int64_t *wn) {
+  if (!ctx || !q) return fail(DG_EINVAL, "NULL argument");
+  if (!aligned16(q)) return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
+  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite");
+  return dg_work_size(ctx, scheme, wn);
+}
+
+extern "C" {
+
+int dg_rk_step(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme, int32_t nsteps,
+               void *hip_stream) {
+  if (!work) return fail(DG_EINVAL, "NULL argument");
+  if (!aligned16(work)) return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
+  int64_t wn = 0;
+  int rc = rk_check(ctx, q, dt, scheme, nsteps, &wn);
+  if (rc != DG_OK) return rc;
+  const size_t bytes = ctx->state_n * ctx->elem_bytes;
+  {
+    const char *a = static_cast<const char *>(q);
+    const char *b = static_cast<const char *>(work);
+    if (a < b + wn * ctx->elem_bytes && b < a + bytes) return fail(DG_EINVAL, "q and work overlap");
+  }
+  return rk_steps(ctx, q, work, dt, scheme, nsteps, static_cast<hipStream_t>(hip_stream));
 }
 
 int dg_rk_stage(dg_ctx *ctx, const void *q, const void *q0, void *out, double c0, double c1,
@@ -515,3 +555,4 @@ int dg_mass(dg_ctx *ctx, const void *q, double out[3], void *hip_stream) {
 }
 
 }  // extern "C"
+

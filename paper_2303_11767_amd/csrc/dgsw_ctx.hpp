@@ -20,7 +20,8 @@ struct dg_ctx {
   double *d_out4 = nullptr;    // mass result
   const void *forcing = nullptr;
   double min_width = 0.0;
-  double *d_proj1 = nullptr;   // [n_lat][2][np]: cos-weighted projection onto order 1
+  double *d_proj = nullptr;    // cos-weighted projection onto order k = 0..7: blocks
+                               // [n_lat][k+1][np] at dgsw::proj_offset(k, n_lat, np)
   double mass_area = 0.0;      // sum over elements of mass_w[j][0]
   int periodic_y = 0;          // 1: the doubly periodic plane
   int kernel = 0;              // DG_KERNEL_LINE or DG_KERNEL_HALF

@@ -185,6 +185,19 @@ int dg_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t step,
   if (rows < 32 || rows % 32 != 0 || rows >= (int64_t(1) << 26))
     return fail(DG_EINVAL, "rows must be a positive multiple of 32");
   if (lr > 0.f && (!adam_m || !adam_v || step < 1)) return fail(DG_EINVAL, "Adam needs m, v and step >= 1");
+  // the output mask (host, read here): weights 0 or 1, at least one 1
+  unsigned bits = 0;
+  int msum = 0;
+  for (int n = 0; n < kOut; ++n) {
+    if (mask[n] == 1.0f) {
+      bits |= 1u << n;
+      ++msum;
+    } else if (mask[n] != 0.0f) {
+      return fail(DG_EINVAL, "mask values must be 0 or 1");
+    }
+  }
+  if (msum == 0) return fail(DG_EINVAL, "mask selects no output");
+  const float scale = 1.0f / ((float)rows * (float)msum);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   TrainWs t = carve_train(workspace, rows, nullptr);
   const int R = (int)rows;
@@ -192,19 +205,9 @@ int dg_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t step,
   if ((e = prep(params, t.w, s)) != hipSuccess) return hip_fail(e, "weight preparation");
   if ((e = dgsw::launch_to_bf16(X, R, kFeatures, kInPad, t.Xb, s)) != hipSuccess) return hip_fail(e, "features");
   if ((e = forward(params, t.w, t.Xb, R, t.Z1, t.H1, t.Z2, t.H2, t.Y, s)) != hipSuccess) return hip_fail(e, "forward");
-  // mean squared error over the unmasked outputs: the mask weights are 0 or 1
-  float msum = 0.f;
-  {
-    float hm[kOut];
-    if ((e = hipMemcpyAsync(hm, mask, sizeof(hm), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-      return hip_fail(e, "mask");
-    for (float v : hm) msum += v;
-  }
-  if (!(msum > 0.f)) return fail(DG_EINVAL, "mask selects no output");
-  const float scale = 1.0f / ((float)R * msum);
+  // mean squared error over the unmasked outputs
   int nb = 0;
-  if ((e = dgsw::launch_mse_grad(t.Y, T, mask, R, kOut, kOutPad, scale, t.dY, t.dYf, t.partial, &nb, s)) != hipSuccess)
+  if ((e = dgsw::launch_mse_grad(t.Y, T, bits, R, kOut, kOutPad, scale, t.dY, t.dYf, t.partial, &nb, s)) != hipSuccess)
     return hip_fail(e, "loss");
   if (loss && (e = dgsw::launch_sum(t.partial, nb, scale, loss, s)) != hipSuccess) return hip_fail(e, "loss sum");
   dgsw::GemmArgs g;
@@ -246,12 +249,15 @@ int dg_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t step,
 int dg_project(const dg_ctx *src, const dg_ctx *dst, const void *q_src, void *q_dst, void *hip_stream) {
   int rc = check_ptrs({src, dst, q_src, q_dst});
   if (rc != DG_OK) return rc;
-  if (dst->np != 2) return fail(DG_EUNSUPPORTED, "projection target must be order 1");
   if (src->levels != 1 || dst->levels != 1) return fail(DG_EUNSUPPORTED, "projection takes one layer");
-  if (src->d.n_lon != dst->d.n_lon || src->d.n_lat != dst->d.n_lat || src->d.dtype != dst->d.dtype)
+  if (src->d.n_lon != dst->d.n_lon || src->d.n_lat != dst->d.n_lat || src->d.dtype != dst->d.dtype ||
+      src->periodic_y != dst->periodic_y)
     return fail(DG_EINVAL, "source and target must share the mesh and dtype");
-  hipError_t e = dgsw::launch_project1(src->d.dtype == DG_F64 ? 0 : 1, q_src, src->d.n_lon, src->E, src->np,
-                                       src->d_proj1, q_dst, static_cast<hipStream_t>(hip_stream));
+  if (q_src == q_dst) return fail(DG_EINVAL, "q_src and q_dst must be different buffers");
+  const int k = dst->np - 1;
+  hipError_t e = dgsw::launch_project(src->d.dtype == DG_F64 ? 0 : 1, q_src, src->d.n_lon, src->E, src->np,
+                                      dst->np, src->d_proj + dgsw::proj_offset(k, src->d.n_lat, src->np), q_dst,
+                                      static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "projection launch");
   return DG_OK;
 }

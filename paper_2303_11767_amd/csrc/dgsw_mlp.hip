@@ -141,16 +141,22 @@ hipError_t launch_gemm(bool a_kc, bool b_kc, int epi, const GemmArgs &g, hipStre
 }
 
 // ------------------------------------------------------------------ fused inference
-// The whole network on 64 rows per workgroup (8 wavefronts): the BF16 inputs
+// The whole network in one persistent kernel: one workgroup of 8 wavefronts
+// per compute unit, looping over tiles of 64 rows.  Each wavefront loads its
+// slice of the three weight matrices into registers once (32 units of both
+// hidden layers, 16 outputs over a quarter of the output layer's rows) and
+// keeps them for every tile, so the weights cross the cache hierarchy once
+// per workgroup instead of once per 64 rows.  Per tile the BF16 inputs
 // (stencil features computed from an r = 1 state, or given FP32 rows) and
-// both hidden layers stay in LDS; only the weights (from L2) and the FP32
-// outputs touch global memory.  Each product is computed transposed,
-// out^T = W in^T: the weights are the MFMA A operand (row = unit, 8
-// consecutive k per lane) and the LDS rows the B operand, so every lane ends
-// with 4 consecutive units of one row and writes them as one 8-byte LDS store.
-// Same rounding points as the unfused path: BF16 inputs, weights and hidden
-// activations, FP32 accumulation, bias and GELU in FP32.
-constexpr int kRows = 64;                 // rows per workgroup
+// both hidden layers stay in LDS; only the inputs and the FP32 outputs touch
+// global memory.  Each product is computed transposed, out^T = W in^T: the
+// weights are the MFMA A operand (row = unit, 8 consecutive k per lane) and
+// the LDS rows the B operand, so every lane ends with 4 consecutive units of
+// one row and writes them as one 8-byte LDS store.  Same rounding points as
+// the unfused path: BF16 inputs, weights and hidden activations, FP32
+// accumulation, bias and GELU in FP32.
+constexpr int kRows = 64;                 // rows per tile
+constexpr int kMlpGrid = 256;             // persistent workgroups: one per MI355X compute unit
 template <typename T>
 struct MlpCorrection {           // the learned stage's correction step (FROM_Q)
   const T *L1;
@@ -165,12 +171,12 @@ constexpr int kWaves = 8;                 // wavefronts per workgroup
 constexpr int kLd = kHidden + 8;          // LDS row stride in BF16 (+16 B: no bank conflicts)
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-// One hidden layer for the 64 rows: wavefront wv computes units
-// [32 wv, 32 wv + 32) of out = gelu(in W^T + b), K inputs per row; the
-// weight fragments are fetched two k-steps ahead.
+// One hidden layer for the 64 rows of a tile: wavefront wv computes units
+// [32 wv, 32 wv + 32) of out = gelu(in W^T + b), K inputs per row, from the
+// weight fragments w[ks][nt] it holds.
 template <int K>
-__device__ __forceinline__ void fused_hidden(const __bf16 *__restrict__ Wt, const float *__restrict__ bias,
-                                             const __bf16 *in, __bf16 *out, int wv, int lane) {
+__device__ __forceinline__ void fused_hidden(const bf16x8 (&w)[K / 32][2], const f32x4 (&bv)[2], const __bf16 *in,
+                                             __bf16 *out, int wv, int lane) {
   constexpr int NT = 2, MT = kRows / 16, KS = K / 32;
   const int r = lane & 15, kq = (lane >> 4) * 8;
   f32x4 acc[NT][MT];
@@ -178,14 +184,6 @@ __device__ __forceinline__ void fused_hidden(const __bf16 *__restrict__ Wt, cons
   for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const __bf16 *wrow[NT];
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) wrow[nt] = Wt + (size_t)(32 * wv + 16 * nt + r) * K + kq;
-  bf16x8 a[KS][NT];
-#pragma unroll
-  for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) a[ks][nt] = *reinterpret_cast<const bf16x8 *>(wrow[nt] + 32 * ks);
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
     bf16x8 b[MT];
@@ -196,19 +194,33 @@ __device__ __forceinline__ void fused_hidden(const __bf16 *__restrict__ Wt, cons
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
-        acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks][nt], b[mt], acc[nt][mt], 0, 0, 0);
+        acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[ks][nt], b[mt], acc[nt][mt], 0, 0, 0);
   }
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     const int n0 = 32 * wv + 16 * nt + (lane >> 4) * 4;
-    const f32x4 bv = *reinterpret_cast<const f32x4 *>(bias + n0);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       bf16x4 h;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) h[i] = (__bf16)gelu_f(acc[nt][mt][i] + bv[i]);
+      for (int i = 0; i < 4; ++i) h[i] = (__bf16)gelu_f(acc[nt][mt][i] + bv[nt][i]);
       *reinterpret_cast<bf16x4 *>(out + (16 * mt + r) * kLd + n0) = h;
     }
+  }
+}
+
+// This wavefront's weight fragments of a hidden layer (units 32 wv ..) and
+// the matching biases.
+template <int K>
+__device__ __forceinline__ void load_hidden(const __bf16 *__restrict__ Wt, const float *__restrict__ bias, int wv,
+                                            int lane, bf16x8 (&w)[K / 32][2], f32x4 (&bv)[2]) {
+  const int r = lane & 15, kq = (lane >> 4) * 8;
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    const __bf16 *row = Wt + (size_t)(32 * wv + 16 * nt + r) * K + kq;
+#pragma unroll
+    for (int ks = 0; ks < K / 32; ++ks) w[ks][nt] = *reinterpret_cast<const bf16x8 *>(row + 32 * ks);
+    bv[nt] = *reinterpret_cast<const f32x4 *>(bias + 32 * wv + 16 * nt + (lane >> 4) * 4);
   }
 }
 
@@ -244,8 +256,9 @@ __device__ __forceinline__ bool correction_row(const float *y, const T *__restri
 
 // FROM_Q: features of the r = 1 state q (as k_features), then the correction
 // of every element (the learned stage): C[rows][12], the workgroup's h-mass
-// of the corrections in partial[blockIdx.x] and the fallback count; else the
-// network on rows of X[rows][108], output Y[rows][32].
+// of the corrections (summed over its tiles in tile order) in
+// partial[blockIdx.x] and the fallback count; else the network on rows of
+// X[rows][108], output Y[rows][32].  Tiles blockIdx.x, blockIdx.x + gridDim.x, ..
 template <typename T, bool FROM_Q>
 __global__ __launch_bounds__(64 * kWaves) void k_mlp_fused(const T *__restrict__ q, int n_lon, int n_lat,
                                                           const float *__restrict__ fmean,
@@ -261,85 +274,116 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_fused(const T *__restrict__
   __shared__ __attribute__((aligned(16))) __bf16 buf1[kRows * kLd];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int e0 = blockIdx.x * kRows;
-  // inputs: one task per (row, stencil neighbour): 12 contiguous values
+  const int r = lane & 15, kq = (lane >> 4) * 8;
+  // the weights, once per workgroup
+  bf16x8 w1[kInPad / 32][2], w2[kHidden / 32][2], w3[kHidden / 32];
+  f32x4 bv1[2], bv2[2];
+  load_hidden<kInPad>(W1t, b1, wv, lane, w1, bv1);
+  load_hidden<kHidden>(W2t, b2, wv, lane, w2, bv2);
+  // output layer: wavefront wv takes rows [16 (wv / 2), +16) and units [16 (wv % 2), +16)
+  const int mt = wv >> 1, nt = wv & 1;
+#pragma unroll
+  for (int ks = 0; ks < kHidden / 32; ++ks)
+    w3[ks] = *reinterpret_cast<const bf16x8 *>(W3t + (size_t)(16 * nt + r) * kHidden + 32 * ks + kq);
+  const int n0 = 16 * nt + (lane >> 4) * 4;
+  const f32x4 bv3 = *reinterpret_cast<const f32x4 *>(b3p + n0);
+  // zero padding of the inputs beyond the 108 features (never overwritten)
   for (int idx = tid; idx < kRows * (kInPad - kFeatures); idx += 64 * kWaves) {
     const int rr = idx / (kInPad - kFeatures);
     buf0[rr * kLd + kFeatures + (idx - rr * (kInPad - kFeatures))] = (__bf16)0.f;
   }
-  for (int task = tid; task < kRows * 9; task += 64 * kWaves) {
-    const int rr = task / 9, sn = task - rr * 9;
-    const int e = e0 + rr < rows ? e0 + rr : rows - 1;
-    float x[12];
-    if constexpr (FROM_Q) {
-      const int dj = sn / 3 - 1, di = sn % 3 - 1;
-      const int j = e / n_lon, i = e - j * n_lon;
-      int jj = j + dj;
-      jj = jj < 0 ? 0 : (jj >= n_lat ? n_lat - 1 : jj);
-      int ii = i + di;
-      ii = ii < 0 ? ii + n_lon : (ii >= n_lon ? ii - n_lon : ii);
-      const T *src = q + ((size_t)jj * n_lon + ii) * 12;
+  double mass = 0.0;          // wavefront 0: this workgroup's h-mass of the corrections
+  bool any_fell = false;
+  unsigned long long fell_count = 0ull;
+  const int ntiles = (rows + kRows - 1) / kRows;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int e0 = tile * kRows;
+    // inputs: one task per (row, stencil neighbour): 12 contiguous values
+    for (int task = tid; task < kRows * 9; task += 64 * kWaves) {
+      const int rr = task / 9, sn = task - rr * 9;
+      const int e = e0 + rr < rows ? e0 + rr : rows - 1;
+      float x[12];
+      if constexpr (FROM_Q) {
+        const int dj = sn / 3 - 1, di = sn % 3 - 1;
+        const int j = e / n_lon, i = e - j * n_lon;
+        int jj = j + dj;
+        jj = jj < 0 ? 0 : (jj >= n_lat ? n_lat - 1 : jj);
+        int ii = i + di;
+        ii = ii < 0 ? ii + n_lon : (ii >= n_lon ? ii - n_lon : ii);
+        const T *src = q + ((size_t)jj * n_lon + ii) * 12;
 #pragma unroll
-      for (int vm = 0; vm < 12; ++vm) x[vm] = (float)src[vm];
+        for (int vm = 0; vm < 12; ++vm) x[vm] = (float)src[vm];
 #pragma unroll
-      for (int vm = 0; vm < 12; ++vm) x[vm] = (x[vm] - fmean[sn * 12 + vm]) * fistd[sn * 12 + vm];
-    } else {
-      const float *src = X + (size_t)e * kFeatures + sn * 12;
+        for (int vm = 0; vm < 12; ++vm) x[vm] = (x[vm] - fmean[sn * 12 + vm]) * fistd[sn * 12 + vm];
+      } else {
+        const float *src = X + (size_t)e * kFeatures + sn * 12;
 #pragma unroll
-      for (int vm = 0; vm < 12; ++vm) x[vm] = src[vm];
-    }
-#pragma unroll
-    for (int vm = 0; vm < 12; ++vm) buf0[rr * kLd + sn * 12 + vm] = (__bf16)x[vm];
-  }
-  __syncthreads();
-  fused_hidden<kInPad>(W1t, b1, buf0, buf1, wv, lane);
-  __syncthreads();
-  fused_hidden<kHidden>(W2t, b2, buf1, buf0, wv, lane);
-  __syncthreads();
-  // output layer: wavefront wv takes rows [16 (wv / 2), +16) and units [16 (wv % 2), +16)
-  const int r = lane & 15, kq = (lane >> 4) * 8;
-  const int mt = wv >> 1, nt = wv & 1;
-  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int k0 = 0; k0 < kHidden; k0 += 32) {
-    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(buf0 + (16 * mt + r) * kLd + k0 + kq);
-    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W3t + (size_t)(16 * nt + r) * kHidden + k0 + kq);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-  }
-  const int n0 = 16 * nt + (lane >> 4) * 4;
-  const f32x4 out = acc + *reinterpret_cast<const f32x4 *>(b3p + n0);
-  if constexpr (!FROM_Q) {
-    const int e = e0 + 16 * mt + r;
-    if (e < rows) *reinterpret_cast<f32x4 *>(Y + (size_t)e * kOutPad + n0) = out;
-  } else {
-    // outputs to LDS (the first hidden layer's buffer is free), then one lane
-    // per row forms its element's correction; wavefront 0 does all 64 rows
-    float *ys = reinterpret_cast<float *>(buf1);
-    *reinterpret_cast<f32x4 *>(ys + (16 * mt + r) * kOutPad + n0) = out;
-    __syncthreads();
-    if (wv == 0) {
-      const int e = e0 + lane;
-      double mass = 0.0;
-      bool fell = false;
-      if (e < rows) {
-        const int j = e / n_lon;
-        float c[12];
-        fell = correction_row<T>(ys + lane * kOutPad, cor.L1 + (size_t)e * 12, cor.omean + j * 12,
-                                 cor.ostd + j * 12, cor.kappa, c);
-        // h-mass of the correction: modes (a, b) = (0, 0) and (0, 1), i.e. 0 and 2
-        mass = cor.mass_w[j * 2 + 1] * (double)c[2];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) cor.C[(size_t)e * 12 + k] = c[k];
+        for (int vm = 0; vm < 12; ++vm) x[vm] = src[vm];
       }
-      const unsigned long long fb = __ballot(fell);
-      if (cor.fallback && lane == 0 && fb != 0ull)
-        atomicAdd(reinterpret_cast<unsigned long long *>(cor.fallback), (unsigned long long)__popcll(fb));
-      // fixed-order (tree) wavefront sum of the 64 rows' masses
+      bf16x4 *dst = reinterpret_cast<bf16x4 *>(buf0 + rr * kLd + sn * 12);
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) mass += __shfl_down(mass, off, 64);
-      if (lane == 0) cor.partial[blockIdx.x] = mass;
+      for (int h4 = 0; h4 < 3; ++h4)
+        dst[h4] = bf16x4{(__bf16)x[4 * h4], (__bf16)x[4 * h4 + 1], (__bf16)x[4 * h4 + 2], (__bf16)x[4 * h4 + 3]};
+    }
+    __syncthreads();
+    fused_hidden<kInPad>(w1, bv1, buf0, buf1, wv, lane);
+    __syncthreads();
+    fused_hidden<kHidden>(w2, bv2, buf1, buf0, wv, lane);
+    __syncthreads();
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < kHidden / 32; ++ks) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8 *>(buf0 + (16 * mt + r) * kLd + 32 * ks + kq);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3[ks], b, acc, 0, 0, 0);
+    }
+    const f32x4 out = acc + bv3;
+    if constexpr (!FROM_Q) {
+      const int e = e0 + 16 * mt + r;
+      if (e < rows) *reinterpret_cast<f32x4 *>(Y + (size_t)e * kOutPad + n0) = out;
+    } else {
+      // outputs to LDS (the first hidden layer's buffer is free), then one
+      // lane per row forms its element's correction (wavefront 0)
+      float *ys = reinterpret_cast<float *>(buf1);
+      *reinterpret_cast<f32x4 *>(ys + (16 * mt + r) * kOutPad + n0) = out;
+      __syncthreads();
+      if (wv == 0) {
+        const int e = e0 + lane;
+        double m = 0.0;
+        bool fell = false;
+        if (e < rows) {
+          const int j = e / n_lon;
+          float c[12];
+          fell = correction_row<T>(ys + lane * kOutPad, cor.L1 + (size_t)e * 12, cor.omean + j * 12,
+                                   cor.ostd + j * 12, cor.kappa, c);
+          // h-mass of the correction: modes (a, b) = (0, 0) and (0, 1), i.e. 0 and 2
+          m = cor.mass_w[j * 2 + 1] * (double)c[2];
+          float4 *cd = reinterpret_cast<float4 *>(cor.C + (size_t)e * 12);
+#pragma unroll
+          for (int k4 = 0; k4 < 3; ++k4) cd[k4] = make_float4(c[4 * k4], c[4 * k4 + 1], c[4 * k4 + 2], c[4 * k4 + 3]);
+        }
+        const unsigned long long fb = __ballot(fell);
+        fell_count += (unsigned long long)__popcll(fb);
+        any_fell = any_fell || fb != 0ull;
+        // fixed-order (tree) wavefront sum of the tile's 64 masses, added in tile order
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m += __shfl_down(m, off, 64);
+        mass += m;
+      }
+    }
+    __syncthreads();   // the next tile overwrites both buffers
+  }
+  if constexpr (FROM_Q) {
+    if (wv == 0 && lane == 0) {
+      cor.partial[blockIdx.x] = mass;
+      if (cor.fallback && any_fell)
+        atomicAdd(reinterpret_cast<unsigned long long *>(cor.fallback), fell_count);
     }
   }
+}
+
+int mlp_fused_blocks(int rows) {
+  const int tiles = (rows + kRows - 1) / kRows;
+  return tiles < kMlpGrid ? tiles : kMlpGrid;
 }
 
 hipError_t launch_mlp_fused(int dtype, const void *q, int n_lon, int n_lat, const float *fmean, const float *fistd,
@@ -349,7 +393,7 @@ hipError_t launch_mlp_fused(int dtype, const void *q, int n_lon, int n_lat, cons
   static_assert(kInPad % 32 == 0 && kHidden == 32 * kWaves && kOutPad == 32 && kRows == 8 * kWaves,
                 "fused network shape");
   if (rows <= 0) return hipSuccess;
-  const dim3 grid((rows + kRows - 1) / kRows), block(64 * kWaves);
+  const dim3 grid(mlp_fused_blocks(rows)), block(64 * kWaves);
   if (!q) {
     hipLaunchKernelGGL((k_mlp_fused<float, false>), grid, block, 0, s, nullptr, 0, 0, nullptr, nullptr, X, rows, W1t,
                        W2t, W3t, b1, b2, b3p, Y, MlpCorrection<float>{});
@@ -394,9 +438,10 @@ hipError_t launch_prep_weights(const float *W, int k_in, int n_out, int kp, int 
 
 // ------------------------------------------------------------------ loss
 // dY = 2 (Y - T) mask / (rows * sum(mask)) as BF16 (padded columns zero) and
-// the squared error summed per block into partial[blockIdx.x].
+// the squared error summed per block into partial[blockIdx.x].  The 0/1 mask
+// of the outputs arrives as bits (bit n: output n counts).
 __global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ Y, const float *__restrict__ T,
-                                                  const float *__restrict__ mask, int rows, int n_out, int ld,
+                                                  unsigned mask_bits, int rows, int n_out, int ld,
                                                   float scale, __bf16 *__restrict__ dY, float *__restrict__ dYf,
                                                   float *__restrict__ partial) {
   __shared__ float sh[256];
@@ -405,8 +450,8 @@ __global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ Y, c
   if (idx < rows * ld) {
     const int m = idx / ld, n = idx - m * ld;
     float g = 0.f;
-    if (n < n_out) {
-      const float d = (Y[(size_t)m * ld + n] - T[(size_t)m * n_out + n]) * mask[n];
+    if (n < n_out && ((mask_bits >> n) & 1u)) {
+      const float d = Y[(size_t)m * ld + n] - T[(size_t)m * n_out + n];
       se = d * d;
       g = 2.f * d * scale;
     }
@@ -422,10 +467,11 @@ __global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ Y, c
   if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
-hipError_t launch_mse_grad(const float *Y, const float *T, const float *mask, int rows, int n_out, int ld, float scale,
-                           __bf16 *dY, float *dYf, float *partial, int *nblocks, hipStream_t s) {
+hipError_t launch_mse_grad(const float *Y, const float *T, unsigned mask_bits, int rows, int n_out, int ld,
+                           float scale, __bf16 *dY, float *dYf, float *partial, int *nblocks, hipStream_t s) {
   *nblocks = (rows * ld + 255) / 256;
-  hipLaunchKernelGGL(k_mse_grad, dim3(*nblocks), dim3(256), 0, s, Y, T, mask, rows, n_out, ld, scale, dY, dYf, partial);
+  hipLaunchKernelGGL(k_mse_grad, dim3(*nblocks), dim3(256), 0, s, Y, T, mask_bits, rows, n_out, ld, scale, dY, dYf,
+                     partial);
   return hipGetLastError();
 }
 
@@ -653,33 +699,36 @@ hipError_t launch_learned_out(int dtype, const LearnedOut &a, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ projection
-// Cos-weighted L2 projection of an order-r state onto order 1 on the same
-// mesh: the longitude degrees a <= 1 are kept (orthonormal), the latitude
-// degrees mix through the per-row 2 x (r+1) matrix Pj[b'][b].
+// Cos-weighted L2 projection of an order-r state onto order k on the same
+// mesh: the longitude degrees a <= min(k, r) are kept (orthonormal, the mass
+// matrix is diagonal in a), the latitude degrees mix through the per-row
+// (k+1) x (r+1) matrix Pj[b'][b].  One thread per output value.
 template <typename T>
-__global__ void k_project1(const T *__restrict__ q, int n_lon, int E, int np, const double *__restrict__ P,
-                           T *__restrict__ out) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= E * 12) return;
-  const int e = idx / 12, k = idx - e * 12;
-  const int v = k / 4, m = k - v * 4, a = m & 1, bp = m >> 1;
+__global__ void k_project(const T *__restrict__ q, int n_lon, int E, int np, int nk,
+                          const double *__restrict__ P, T *__restrict__ out) {
+  const int per = 3 * nk * nk;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)E * per) return;
+  const int e = (int)(idx / per), k = (int)(idx - (long long)e * per);
+  const int v = k / (nk * nk), m = k - v * nk * nk, bp = m / nk, a = m - bp * nk;
   const int j = e / n_lon;
   const T *qe = q + (size_t)e * 3 * np * np + (size_t)v * np * np;
   double acc = 0.0;
   if (a < np)
-    for (int b = 0; b < np; ++b) acc += P[((size_t)j * 2 + bp) * np + b] * (double)qe[b * np + a];
+    for (int b = 0; b < np; ++b) acc += P[((size_t)j * nk + bp) * np + b] * (double)qe[b * np + a];
   out[idx] = (T)acc;
 }
 
-hipError_t launch_project1(int dtype, const void *q, int n_lon, int E, int np, const double *P, void *out,
-                           hipStream_t s) {
-  const int blocks = (E * 12 + 255) / 256;
+hipError_t launch_project(int dtype, const void *q, int n_lon, int E, int np, int nk, const double *P,
+                          void *out, hipStream_t s) {
+  const long long n = (long long)E * 3 * nk * nk;
+  const int blocks = (int)((n + 255) / 256);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_project1<double>, dim3(blocks), dim3(256), 0, s, static_cast<const double *>(q), n_lon, E, np,
-                       P, static_cast<double *>(out));
+    hipLaunchKernelGGL(k_project<double>, dim3(blocks), dim3(256), 0, s, static_cast<const double *>(q), n_lon, E,
+                       np, nk, P, static_cast<double *>(out));
   else
-    hipLaunchKernelGGL(k_project1<float>, dim3(blocks), dim3(256), 0, s, static_cast<const float *>(q), n_lon, E, np,
-                       P, static_cast<float *>(out));
+    hipLaunchKernelGGL(k_project<float>, dim3(blocks), dim3(256), 0, s, static_cast<const float *>(q), n_lon, E,
+                       np, nk, P, static_cast<float *>(out));
   return hipGetLastError();
 }
 

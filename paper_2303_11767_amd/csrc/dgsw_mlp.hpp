@@ -33,8 +33,10 @@ struct CorrectionArgs {
   double *partial;               // one h-mass per workgroup: mlp_fused_blocks(E)
   int64_t *fallback;             // optional device counter (64-bit: never wraps)
 };
-inline int mlp_fused_blocks(int rows) { return (rows + 63) / 64; }
-// Whole-network inference, 64 rows per workgroup, activations in LDS.  With q:
+// workgroups of the persistent network kernel for `rows` rows (at most one
+// per compute unit)
+int mlp_fused_blocks(int rows);
+// Whole-network inference, tiles of 64 rows, activations in LDS.  With q:
 // rows = elements of the r = 1 state q (dtype 0/1), features computed from q,
 // then the correction of each element (ca required; Y unused).  With q == NULL:
 // rows of X[rows][108] (FP32) -> Y[rows][32] FP32 (the first 12 used).
@@ -44,8 +46,8 @@ hipError_t launch_mlp_fused(int dtype, const void *q, int n_lon, int n_lat, cons
                             const CorrectionArgs *ca);
 hipError_t launch_prep_weights(const float *W, int k_in, int n_out, int kp, int np_, __bf16 *Wt, __bf16 *Wr,
                                hipStream_t s);
-hipError_t launch_mse_grad(const float *Y, const float *T, const float *mask, int rows, int n_out, int ld, float scale,
-                           __bf16 *dY, float *dYf, float *partial, int *nblocks, hipStream_t s);
+hipError_t launch_mse_grad(const float *Y, const float *T, unsigned mask_bits, int rows, int n_out, int ld,
+                           float scale, __bf16 *dY, float *dYf, float *partial, int *nblocks, hipStream_t s);
 hipError_t launch_colsum(const float *G, int rows, int n, int ld, float *out, hipStream_t s);
 hipError_t launch_sum(const float *p, int n, float scale, float *out, hipStream_t s);
 hipError_t launch_to_bf16(const float *X, int rows, int n, int ldx, __bf16 *Xb, hipStream_t s);
@@ -57,8 +59,8 @@ hipError_t launch_features(int dtype, const void *q, int n_lon, int n_lat, const
                            int ldx, __bf16 *X, hipStream_t s);
 hipError_t launch_features_f32(int dtype, const void *q, int n_lon, int n_lat, const float *mean, const float *istd,
                                float *X, hipStream_t s);
-hipError_t launch_project1(int dtype, const void *q, int n_lon, int E, int np, const double *P, void *out,
-                           hipStream_t s);
+hipError_t launch_project(int dtype, const void *q, int n_lon, int E, int np, int nk, const double *P,
+                          void *out, hipStream_t s);
 
 // The learned stage's last step: out = L1 + C, the (h, 00) entry replaced by
 // the global h-mass delta formed from the per-workgroup partials, or the

@@ -4,6 +4,7 @@
 // also builds and runs on its own for host-side checks.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 
@@ -11,6 +12,13 @@ namespace dgsw {
 
 constexpr int kMaxOrder = 7;
 constexpr int kMaxNP = kMaxOrder + 1;
+
+// Layout of a context's projection tables: for each target order k = 0..7 a
+// block [n_lat][k+1][np]; the blocks are stored one after the other.
+constexpr int proj_rows_total() { return (kMaxNP * (kMaxNP + 1)) / 2; }
+inline size_t proj_offset(int k, int n_lat, int np) {
+  return (size_t)n_lat * np * (size_t)((k * (k + 1)) / 2);
+}
 
 // n-point Gauss-Legendre rule on [-1, 1] by Newton iteration on P_n from
 // Chebyshev initial guesses; nodes ascending.

@@ -67,18 +67,24 @@ def mlp_forward(params, X, out=None, stream=None):
 
 def mlp_train_step(params, X, T, mask, adam_m=None, adam_v=None, step=0, lr=0.0, grads=None,
                    loss=None, stream=None):
-    """Forward + backward (+ Adam when lr > 0) on one batch (rows % 32 == 0)."""
+    """Forward + backward (+ Adam when lr > 0) on one batch (rows % 32 == 0).
+    mask: 12 host values, 0 or 1 (a sequence or a CPU array)."""
     rows = X.shape[0]
     P = param_count()
     ws = _mlp_ws(rows, X.device)
+    m = [float(v) for v in mask]
+    if len(m) != N_OUT:
+        raise ValueError(f"mask needs {N_OUT} values")
+    mask_h = (ctypes.c_float * N_OUT)(*m)
     check(load().dg_mlp_train_step(
         _f32(params, P, "params"), _ptr(adam_m), _ptr(adam_v), int(step), float(lr),
-        _f32(X, rows * N_IN, "X"), _f32(T, rows * N_OUT, "T"), _f32(mask, N_OUT, "mask"), rows,
+        _f32(X, rows * N_IN, "X"), _f32(T, rows * N_OUT, "T"), mask_h, rows,
         _ptr(grads), _ptr(loss), _ptr(ws), _stream_handle(stream)))
 
 
 def project(src, dst, q_src, q_dst=None, stream=None):
-    """Cos-weighted projection of src's state onto dst's order-1 basis."""
+    """Cos-weighted projection of src's state onto dst's basis (dst's order,
+    same mesh; a target order at or above src's embeds the state)."""
     if q_dst is None:
         q_dst = dst.empty_state(q_src.device)
     check(load().dg_project(src._ctx, dst._ctx, src._ptr(q_src, "q_src"), dst._ptr(q_dst, "q_dst"),

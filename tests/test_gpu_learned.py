@@ -95,7 +95,7 @@ def test_gradients_match_oracle(dg, rows):
     P = learned.param_count()
     grads = torch.zeros(P, dtype=torch.float32, device="cuda")
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-    learned.mlp_train_step(dev(flat(p)), dev(X), dev(T), dev(mask), grads=grads, loss=loss)
+    learned.mlp_train_step(dev(flat(p)), dev(X), dev(T), mask, grads=grads, loss=loss)
     Y, cache = mlp.forward(p, X)
     g = mlp.backward(p, cache, Y, T, mask)
     assert abs(loss.item() - mlp.loss(Y, T, mask)) <= 1e-4 * mlp.loss(Y, T, mask)
@@ -121,7 +121,7 @@ def test_adam_step_matches_oracle(dg):
     grads = torch.zeros(P, dtype=torch.float32, device="cuda")
     state = {}
     for step in (1, 2, 3):
-        learned.mlp_train_step(pd, dev(X), dev(T), dev(mask), m, v, step, 1e-3, grads=grads)
+        learned.mlp_train_step(pd, dev(X), dev(T), mask, m, v, step, 1e-3, grads=grads)
         mlp.adam(p, unflat(grads.cpu().numpy().astype(np.float64)), state)
     err = np.abs(pd.cpu().numpy() - flat(p)).max()
     say("  max param difference after 3 steps", err)
@@ -170,6 +170,29 @@ def test_features_and_projection_match_oracle(dg):
         np.testing.assert_allclose(X, mlp.stencil_features(q1, n_lon, n_lat), rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("src,dst", [(4, 0), (4, 2), (4, 3), (5, 2), (5, 3), (5, 4), (2, 4), (3, 3)])
+def test_projection_any_target_order(dg, src, dst):
+    """dg_project onto orders other than 1: the cos-weighted projection of
+    the oracle (targets below the source), the unchanged state embedded
+    with zeros (targets at or above it)."""
+    dgm, learned = dg
+    n_lon, n_lat = 18, 9
+    say("projection", src, "->", dst)
+    q, _ = band_limited_state(n_lon, n_lat, src, 6, 23)
+    ms, md = dgm.Mesh(n_lon, n_lat, src), dgm.Mesh(n_lon, n_lat, dst)
+    got = learned.project(ms, md, torch.from_numpy(q).cuda()).cpu().numpy()
+    ref = project_order(q, SphereDG(n_lon, n_lat, src), SphereDG(n_lon, n_lat, dst))
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say("  rel err", err)
+    assert err <= 1e-13
+    if dst >= src:
+        ns, nd = src + 1, dst + 1
+        emb = np.zeros_like(got)
+        for b in range(ns):
+            emb[:, :, b * nd:b * nd + ns] = q[:, :, b * ns:(b + 1) * ns]
+        assert np.array_equal(got, emb)
+
+
 def _learned_setup(dg, kappa, params=None, dtype="f64"):
     dgm, learned = dg
     n_lon, n_lat = 36, 18
@@ -212,14 +235,26 @@ def test_learned_rhs_fallback_and_mass(dg):
     plain3 = mesh3.rhs(q3)
     m_plain = mesh3.mass(plain3)[0]
     m_learn = mesh3.mass(out3)[0]
-    # the correction's own h-mass, element by element in absolute value: the
-    # scale of the roundoff left after the global (h, mode 00) fix (FP64)
+    # element contributions R^2 2 (M x)_00 of the h tendency, in absolute
+    # value and summed: the correction's own (the size of what the
+    # (h, mode 00) fix cancels) and those of the two FP64 mass sums being
+    # compared (their rounding scale: the plain tendencies of neighbouring
+    # elements cancel to a total far below their sum)
     o = SphereDG(mesh3.n_lon, mesh3.n_lat, 1)
-    d = o.grid((out3 - plain3).cpu().numpy())[:, :, 0]               # [j, i, 4]
-    m_abs = o.R ** 2 * 2.0 * np.abs(np.einsum("jn,jin->ji", o.M[:, 0, :], d)).sum()
-    say("  h-mass tendency plain", m_plain, "learned", m_learn, "correction |mass|", m_abs)
+
+    def abs_mass(x):
+        d = o.grid(x.cpu().numpy())[:, :, 0]                            # [j, i, 4]
+        return o.R ** 2 * 2.0 * np.abs(np.einsum("jn,jin->ji", o.M[:, 0, :], d)).sum()
+
+    m_abs = abs_mass(out3 - plain3)
+    scale = abs_mass(out3) + abs_mass(plain3) + m_abs
+    eps = np.finfo(np.float64).eps
+    say("  h-mass tendency plain", m_plain, "learned", m_learn, "correction |mass|", m_abs,
+        "rounding scale eps *", scale)
     assert m_abs > 0
-    assert abs(m_learn - m_plain) <= 1e-13 * m_abs + 1e-13 * abs(m_plain)
+    # an FP32-rounded fix would leave ~6e-8 m_abs, an unfixed one ~m_abs
+    assert abs(m_learn - m_plain) <= 4.0 * eps * scale
+    assert 4.0 * eps * scale < 1e-9 * m_abs
 
 
 def test_learned_rhs_matches_oracle(dg):
