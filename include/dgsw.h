@@ -191,6 +191,22 @@ int dg_rhs(dg_ctx *ctx, const void *q, void *dqdt, void *hip_stream);
 int dg_rk_step(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme,
                int32_t nsteps, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dg_rk_step
+ * without the `work` argument.  The scheme's stage states live in a library
+ * array of DG_NOALLOC_SCRATCH_BYTES per GPU (held from library load until the
+ * process ends), so the call allocates and frees nothing; results equal
+ * dg_rk_step's bit for bit (same kernels, same order).  Limit: dg_work_size
+ * values of the ctx dtype must fit DG_NOALLOC_SCRATCH_BYTES (32 MiB: e.g. an
+ * r = 3 mesh of 180 x 90 elements in FP64 with RK4), else DG_EINVAL and
+ * nothing is enqueued.  Every call on one GPU shares that GPU's array: calls
+ * that overlap in time on one GPU (other streams, other host threads) race
+ * and give undefined results; calls in order on one stream are safe.  Other
+ * arguments and errors as dg_rk_step. */
+#define DG_NOALLOC_SCRATCH_BYTES 33554432
+int dg_rk_step_noalloc(dg_ctx *ctx, void *q, double dt, int32_t scheme, int32_t nsteps,
+                       void *hip_stream);
+
 /* One Runge-Kutta stage in Shu-Osher form, the building block of
  * dg_rk_step: out = c0 * q0 + c1 * (q + dt * L(q)), L(q) = M^-1 h(q)
  * (+ forcing).  q0 may be NULL iff c0 == 0; q0 may be the same buffer as

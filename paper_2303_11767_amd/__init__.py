@@ -197,6 +197,13 @@ class Mesh:
                                    float(dt), int(scheme), int(nsteps), _stream_handle(stream)))
         return q
 
+    def rk_step_noalloc(self, q, dt, scheme=DG_SSP_RK3, nsteps=1, stream=None):
+        """rk_step with the stage states in the library's per-GPU scratch
+        array (no work argument, nothing allocated)."""
+        check(self._lib.dg_rk_step_noalloc(self._ctx, self._ptr(q, "q"), float(dt), int(scheme),
+                                           int(nsteps), _stream_handle(stream)))
+        return q
+
     def mass(self, q, stream=None):
         """(h, hu, hv) integrals times R^2; synchronises the stream."""
         out = (ctypes.c_double * 3)()

@@ -33,7 +33,8 @@ EXPORTS = ("dg_init_mesh", "dg_init_plane", "dg_set_kernel", "dg_get_kernel", "d
            "dg_graph_launch", "dg_graph_free", "dg_mlp_param_count", "dg_mlp_workspace_size",
            "dg_mlp_forward", "dg_mlp_train_step", "dg_project", "dg_features",
            "dg_learned_workspace_size", "dg_rhs_learned", "dg_rk_step_learned",
-           "dg_adv_init", "dg_adv_free", "dg_adv_state_size", "dg_adv_rhs", "dg_adv_rk_step")
+           "dg_adv_init", "dg_adv_free", "dg_adv_state_size", "dg_adv_rhs", "dg_adv_rk_step",
+           "dg_rk_step_noalloc")
 
 
 class Learned(ctypes.Structure):
@@ -97,6 +98,7 @@ def load():
     lib.dg_rk_stage.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, vp]
     lib.dg_rk_step.argtypes = [vp, vp, vp, ctypes.c_double, i32, i32, vp]
+    lib.dg_rk_step_noalloc.argtypes = [vp, vp, ctypes.c_double, i32, i32, vp]
     lib.dg_mass.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.dg_set_forcing.argtypes = [vp, vp]
     dp = ctypes.POINTER(ctypes.c_double)

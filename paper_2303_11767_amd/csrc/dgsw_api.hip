@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -442,7 +443,8 @@ int dg_rhs(dg_ctx *ctx, const void *q, void *dqdt, void *hip_stream) {
 }  // extern "C"
 
 // nsteps steps of the scheme on q with the stage states in work (already
-// checked: dg_work_size values, not overlapping q); shared by dg_rk_step.
+// checked: dg_work_size values, not overlapping q); shared by dg_rk_step and
+// dg_rk_step_noalloc.
 static int rk_steps(dg_ctx *ctx, void *q, void *work, double dt, int32_t scheme, int32_t nsteps,
                     hipStream_t s) {
   int rc = DG_OK;
@@ -556,3 +558,52 @@ int dg_mass(dg_ctx *ctx, const void *q, double out[3], void *hip_stream) {
 
 }  // extern "C"
 
+// ------------------------------------------------------------------ no-allocation RK step
+// Stage states of dg_rk_step_noalloc: one array per GPU, loaded with the
+// library and held until the process ends.  Host code never uses the array's
+// name as an address: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and kept in g_scratch.
+static __device__ __align__(256) unsigned char scratch[DG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array (looked up on the first call on
+// the device), or an error code.
+int scratch_ptr(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(DG_EUNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress of the no-allocation scratch");
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return DG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int dg_rk_step_noalloc(dg_ctx *ctx, void *q, double dt, int32_t scheme, int32_t nsteps,
+                       void *hip_stream) {
+  int64_t wn = 0;
+  int rc = rk_check(ctx, q, dt, scheme, nsteps, &wn);
+  if (rc != DG_OK) return rc;
+  const uint64_t need = (uint64_t)wn * ctx->elem_bytes;
+  if (need > (uint64_t)DG_NOALLOC_SCRATCH_BYTES)
+    return fail(DG_EINVAL, "dg_rk_step_noalloc: the scheme's stage states need " + std::to_string(need) +
+                               " bytes, more than the " + std::to_string((long long)DG_NOALLOC_SCRATCH_BYTES) +
+                               "-byte scratch; use dg_rk_step with a caller work buffer");
+  void *work = nullptr;
+  if ((rc = scratch_ptr(&work)) != DG_OK) return rc;
+  return rk_steps(ctx, q, work, dt, scheme, nsteps, static_cast<hipStream_t>(hip_stream));
+}
+
+}  // extern "C"
