@@ -374,8 +374,17 @@ def ensemble_section(steps=10):
     g = ens.graph(q, work, nsteps=steps)
     t_graph = timed(lambda n: g.launch())
     g.close()
+    orders = sorted({m.order for m in ens.members})
+    layouts = {o: ens.kernel(o) for o in orders}
+    # the single fused launch over all orders (line layout only)
+    ens.set_schedule(schedule[0], 0, False)
+    for o in orders:
+        ens.set_kernel(o, "line")
     ens.set_schedule(schedule[0], schedule[1], True)
     t_fused = timed(lambda n: ens.rk_step(q, work, nsteps=n))
+    ens.set_schedule(schedule[0], 0, False)
+    for o in orders:
+        ens.set_kernel(o, layouts[o])
     ens.set_schedule(*schedule)
     views = ens.views(q)
     works = [m.empty_work() for m in ens.members]
@@ -395,7 +404,7 @@ def ensemble_section(steps=10):
                          "alg_bytes_per_step": alg, "kernels": "k_ens_stage* (batched schedule)"},
             "batched_over_plain": t_plain / t_best,
             "schedule": {"waves_per_group": schedule[0], "groups": schedule[1],
-                         "fused": schedule[2]},
+                         "fused": schedule[2], "layouts": {str(o): layouts[o] for o in orders}},
             "ms_per_step": {"batched": t_ens * 1e3, "batched_graph": t_graph * 1e3,
                             "fused_single_launch": t_fused * 1e3, "plain_per_member": t_plain * 1e3},
             "dof_updates_per_s": {"batched": 3 * dofs / t_ens, "plain_per_member": 3 * dofs / t_plain},
@@ -588,6 +597,104 @@ def profile_probe(args):
                       "stage_launches": 3 * args.steps}), flush=True)
 
 
+def profile_probe_learned(args):
+    """Short run for rocprofv3 passes over the learned stage: `steps`
+    SSP-RK3 steps of the learned r = 1 form on 360 x 180 elements (FP64,
+    stored model), then `steps` training steps of the network on 8192 random
+    standardised rows (the training GEMMs), then the calibration copies."""
+    import numpy as np
+    import torch
+
+    import paper_2303_11767_amd as dg
+    from paper_2303_11767_amd import learned
+    from paper_2303_11767_amd import train_learned as tl
+    from dg_inputs import band_limited_state
+    model, meta = tl.load_model(LEARNED_MODEL)
+    m1 = dg.Mesh(tl.N_LON, tl.N_LAT, 1, dtype="f64")
+    net = learned.LearnedRHS(m1, model["params"], model["feat_mean"], model["feat_istd"],
+                             model["out_mean"], model["out_std"], kappa=meta.get("kappa", 1.0))
+    qh, info = band_limited_state(tl.N_LON, tl.N_LAT, 1, tl.L_MAX, 200)
+    q = torch.from_numpy(qh).cuda()
+    dt = dg.cfl_time_step(m1, info.cmax, CFL)
+    work = m1.empty_work()
+    net.rk_step(q, work, dt, nsteps=args.steps)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    rows = 8192
+    X = torch.from_numpy(rng.standard_normal((rows, 108)).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.standard_normal((rows, 12)).astype(np.float32)).cuda()
+    P = learned.param_count()
+    params = model["params"].clone()
+    mom, var = torch.zeros(P, device="cuda"), torch.zeros(P, device="cuda")
+    for step in range(1, args.steps + 1):
+        learned.mlp_train_step(params, X, T, tl.MASK, mom, var, step, 1e-4)
+    torch.cuda.synchronize()
+    nbytes = 256 << 20
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "done", "learned_stages": 3 * args.steps, "train_steps": args.steps,
+                      "rows": int(m1.E), "copy_bytes": nbytes}), flush=True)
+
+
+def profile_probe_ensemble(args):
+    """Short run for rocprofv3 passes over the ensemble kernels: the 64-member
+    FP32 ensemble of the benchmark with every member at rest (the kernels run
+    the same instructions on any state), autotuned, then `steps` SSP-RK3
+    steps, then the calibration copies."""
+    import torch
+
+    import paper_2303_11767_amd as dg
+    from dg_inputs import ensemble_members, lake_at_rest_state
+    mem = ensemble_members(64, seed=4)
+    ens = dg.Ensemble(mem, dtype="f32", h_ref=1e4)
+    q = ens.empty_state()
+    for m, v in zip(ens.members, ens.views(q)):
+        v.copy_(torch.from_numpy(lake_at_rest_state(m.n_lon, m.n_lat, m.order)).to(v.dtype))
+    ens.set_dt([1.0] * ens.n)
+    work = ens.empty_work()
+    schedule = ens.autotune(q, work)
+    ens.rk_step(q, work, nsteps=args.steps)
+    torch.cuda.synchronize()
+    nbytes = 256 << 20
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    orders = sorted({m.order for m in ens.members})
+    print(json.dumps({"probe": "done", "schedule": schedule, "layouts": {o: ens.kernel(o) for o in orders},
+                      "state_bytes": ens.size * 4, "steps": args.steps, "copy_bytes": nbytes}), flush=True)
+
+
+def probe_contraction(n_elem=64800, reps=50):
+    """The volume-integral contraction alone at r = 5 in FP32 on the elements
+    of the 360 x 180 mesh, in the sum-factorised VALU form the stage kernels
+    use and in the dense MFMA form (libdgsw_probe.so; nodal values synthesised
+    in registers, so no memory traffic): time per launch of each, and the
+    largest difference between their results."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2303_11767_amd", "libdgsw_probe.so"))
+    lib.dgp_contraction_time.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_double)]
+    lib.dgp_contraction_check.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    out = {"probe": "contraction r=5 FP32", "n_elem": n_elem, "reps": reps}
+    for name, variant in (("valu_sum_factorised", 0), ("mfma_dense", 1)):
+        ms = ctypes.c_double()
+        rc = lib.dgp_contraction_time(variant, n_elem, reps, ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"contraction probe {name}: error {rc}")
+        out[name] = {"us_per_launch": ms.value * 1e3, "ns_per_element": ms.value * 1e6 / n_elem}
+    rel = ctypes.c_double()
+    if lib.dgp_contraction_check(4096, ctypes.byref(rel)) != 0:
+        raise RuntimeError("contraction probe check failed")
+    out["max_rel_difference"] = rel.value
+    out["mfma_over_valu_time"] = out["mfma_dense"]["us_per_launch"] / out["valu_sum_factorised"]["us_per_launch"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -605,6 +712,14 @@ def main():
                     help="short run for rocprofv3 counter passes (prints no bench line)")
     ap.add_argument("--probe-mesh", default=None, metavar="NLONxNLATxR",
                     help="mesh of the profile probe (default: the benchmark mesh)")
+    ap.add_argument("--probe-contraction", action="store_true",
+                    help="time the r = 5 FP32 volume contraction in its VALU and MFMA forms "
+                         "(prints no bench line)")
+    ap.add_argument("--probe-ensemble", action="store_true",
+                    help="short run of the 64-member ensemble for rocprofv3 passes (prints no bench line)")
+    ap.add_argument("--probe-learned", action="store_true",
+                    help="short run of the learned stage and the network's training step "
+                         "for rocprofv3 passes (prints no bench line)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -613,6 +728,15 @@ def main():
         sys.exit(2)
     if args.profile_probe:
         profile_probe(args)
+        return
+    if args.probe_learned:
+        profile_probe_learned(args)
+        return
+    if args.probe_contraction:
+        probe_contraction()
+        return
+    if args.probe_ensemble:
+        profile_probe_ensemble(args)
         return
     pool = futs = None
     if not args.no_extras:

@@ -267,16 +267,25 @@ int dg_ens_rk_stage(dg_ens *ens, const void *q, const void *q0, void *out, doubl
 int dg_ens_rk_step(dg_ens *ens, void *q, void *work, int32_t nsteps, void *hip_stream);
 /* Schedule of the persistent kernels: wavefronts per workgroup (1, 2 or 4),
  * workgroups in total (each takes one contiguous, cost-balanced range of the
- * work list, sorted by order; 0 = one workgroup per waves_per_group items, the
- * default), and fused = 1 for a single launch covering all
- * orders (its register budget is that of the union of the orders) or 0 for one
- * launch per distinct order (each compiled for that order alone). */
+ * work list, sorted by order and layout; 0 = one workgroup per
+ * waves_per_group items, the default), and fused = 1 for a single launch
+ * covering all orders (its register budget is that of the union of the
+ * orders; line-layout members only, else DG_EINVAL) or 0 for one launch per
+ * distinct (order, layout) (each compiled for that pair alone). */
 int dg_ens_set_schedule(dg_ens *ens, int32_t waves_per_group, int32_t groups, int32_t fused);
 int dg_ens_get_schedule(const dg_ens *ens, int32_t *waves_per_group, int32_t *groups,
                         int32_t *fused);
-/* Pick the fastest schedule by timing stages on q (read only) and work (2
- * packed states, overwritten); with cache_path, reuse or record the choice
- * keyed by the device and the member list.  Synchronises hip_stream. */
+/* Stage-kernel layout (DG_KERNEL_*, as dg_set_kernel) of every member of the
+ * given order; at dg_ens_init each member takes the layout a single mesh of
+ * its size and order would take.  DG_EINVAL if no member has that order, if
+ * the schedule is the fused launch and kernel is not DG_KERNEL_LINE, or while
+ * graphs of the ensemble are live.  The schedule's settings are kept. */
+int dg_ens_set_kernel(dg_ens *ens, int32_t order, int32_t kernel);
+int dg_ens_get_kernel(const dg_ens *ens, int32_t order, int32_t *kernel);
+/* Pick the fastest layout per order, then the fastest schedule, by timing
+ * stages on q (read only) and work (2 packed states, overwritten); with
+ * cache_path, reuse or record the choice keyed by the device and the member
+ * list.  Synchronises hip_stream. */
 int dg_ens_autotune(dg_ens *ens, const void *q, void *work, const char *cache_path,
                     void *hip_stream);
 
@@ -287,8 +296,8 @@ int dg_ens_autotune(dg_ens *ens, const void *q, void *work, const char *cache_pa
  * A graph pins the context or ensemble it was captured on: dg_free /
  * dg_ens_free called while graphs of it are live return DG_OK but defer the
  * release of its device tables to the last dg_graph_free, and
- * dg_ens_set_schedule / dg_ens_autotune return DG_EINVAL while graphs of
- * the ensemble are live (the schedule is baked into them).  Capturing on an
+ * dg_ens_set_schedule / dg_ens_set_kernel / dg_ens_autotune return DG_EINVAL
+ * while graphs of the ensemble are live (the schedule is baked into them).  Capturing on an
  * object whose free was deferred returns DG_EINVAL.
  * ------------------------------------------------------------------------- */
 typedef struct dg_graph dg_graph;

@@ -106,25 +106,27 @@ class Mesh:
         self._forcing = None
 
     # -- stage-kernel layout
+    _KERNELS = ("line", "half")
+
     @property
     def kernel(self):
         """"line" (r+1 lanes per element) or "half" (2(r+1) lanes)."""
         k = ctypes.c_int32()
         check(self._lib.dg_get_kernel(self._ctx, ctypes.byref(k)))
-        return "half" if k.value == 1 else "line"
+        return self._KERNELS[k.value]
 
     @kernel.setter
     def kernel(self, name):
-        check(self._lib.dg_set_kernel(self._ctx, {"line": 0, "half": 1}[name]))
+        check(self._lib.dg_set_kernel(self._ctx, self._KERNELS.index(name)))
 
     def autotune(self, q, stream=None):
-        """Time both stage-kernel layouts on q (read only) and keep the
-        faster (dg_autotune); returns its name.  Synchronises the stream."""
+        """Time the stage-kernel layouts on q (read only) and keep the
+        fastest (dg_autotune); returns its name.  Synchronises the stream."""
         work = self.empty_work(DG_SSP_RK3, q.device)
         k = ctypes.c_int32()
         check(self._lib.dg_autotune(self._ctx, self._ptr(q, "q"), self._ptr(work, "work", self.work_size()),
                                     ctypes.byref(k), _stream_handle(stream)))
-        return "half" if k.value == 1 else "line"
+        return self._KERNELS[k.value]
 
     # -- identical vertical layers (dg_set_levels)
     @property
@@ -407,6 +409,15 @@ class Ensemble:
     def set_schedule(self, waves_per_group, groups, fused=False):
         check(self._lib.dg_ens_set_schedule(self._e, int(waves_per_group), int(groups),
                                             int(bool(fused))))
+
+    def set_kernel(self, order, name):
+        """Stage-kernel layout ("line" or "half") of every member of `order`."""
+        check(self._lib.dg_ens_set_kernel(self._e, int(order), Mesh._KERNELS.index(name)))
+
+    def kernel(self, order):
+        k = ctypes.c_int32()
+        check(self._lib.dg_ens_get_kernel(self._e, int(order), ctypes.byref(k)))
+        return Mesh._KERNELS[k.value]
 
     def schedule(self):
         """(waves per workgroup, workgroups, fused)."""

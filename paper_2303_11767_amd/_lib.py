@@ -29,6 +29,7 @@ EXPORTS = ("dg_init_mesh", "dg_init_plane", "dg_set_kernel", "dg_get_kernel", "d
            "dg_rk_stage", "dg_rk_step", "dg_mass", "dg_set_forcing", "dg_last_error",
            "dg_ens_init", "dg_ens_free", "dg_ens_state_size", "dg_ens_offsets", "dg_ens_member",
            "dg_ens_set_dt", "dg_ens_rhs", "dg_ens_rk_stage", "dg_ens_rk_step", "dg_ens_set_schedule",
+           "dg_ens_set_kernel", "dg_ens_get_kernel",
            "dg_ens_get_schedule", "dg_ens_autotune", "dg_graph_rk", "dg_graph_ens",
            "dg_graph_launch", "dg_graph_free", "dg_mlp_param_count", "dg_mlp_workspace_size",
            "dg_mlp_forward", "dg_mlp_train_step", "dg_project", "dg_features",
@@ -114,6 +115,8 @@ def load():
     lib.dg_ens_rk_step.argtypes = [vp, vp, vp, i32, vp]
     lib.dg_ens_set_schedule.argtypes = [vp, i32, i32, i32]
     lib.dg_ens_get_schedule.argtypes = [vp, i32p, i32p, i32p]
+    lib.dg_ens_set_kernel.argtypes = [vp, i32, i32]
+    lib.dg_ens_get_kernel.argtypes = [vp, i32, i32p]
     lib.dg_ens_autotune.argtypes = [vp, vp, vp, ctypes.c_char_p, vp]
     lib.dg_graph_rk.argtypes = [vp, vp, vp, ctypes.c_double, i32, i32, ctypes.POINTER(vp)]
     lib.dg_graph_ens.argtypes = [vp, vp, vp, i32, ctypes.POINTER(vp)]

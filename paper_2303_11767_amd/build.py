@@ -14,6 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdgsw.so")
+PROBE_SRC = "probe_contraction.hip"
+PROBE_LIB = os.path.join(PKG, "libdgsw_probe.so")
 SOURCES = ["dgsw_tables.cpp", "dgsw_kernels.hip", "dgsw_ens_kernels.hip", "dgsw_api.hip",
            "dgsw_ensemble.hip", "dgsw_mlp.hip", "dgsw_learned.hip", "dgsw_advection.hip"]
 ARCH = os.environ.get("DGSW_OFFLOAD_ARCH", "gfx950")
@@ -53,6 +55,10 @@ def build(verbose=False, jobs=None):
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "--offload-arch=" + ARCH, "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)
+    # the contraction-throughput probe: a measurement, not part of the solver
+    ptmp = PROBE_LIB + ".tmp"
+    _run([HIPCC] + COMMON + DEVICE + ["-shared", "-o", ptmp, os.path.join(CSRC, PROBE_SRC)], verbose)
+    os.replace(ptmp, PROBE_LIB)
     return LIB
 
 

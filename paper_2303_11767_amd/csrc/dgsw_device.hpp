@@ -66,13 +66,16 @@ hipError_t launch_stage(int dtype, int np, const StageLaunch &a, hipStream_t s);
 
 // One work item of the ensemble kernels: one wavefront of one member, with
 // everything the wavefront needs (a single 64-byte scalar load).
+// One wavefront of one member.  Line layout: row j, segment seg.  Half
+// layout: the elements seg .. e_end - 1 from row j on (packed across a row
+// end, or one row's segment when e_end is that row's end).
 struct alignas(16) EnsItem {
   const void *glob;   // GlobTab<T, np>
   const void *rows;   // RowTab<T, np>[n_lat]
   long long off;      // offset of the member's state in the packed buffers (values)
   double dt;
   int n_lon, n_lat, np, j;
-  int seg, alpha_global, member, pad;
+  int seg, alpha_global, member, e_end;
 };
 
 struct EnsLaunch {
@@ -89,8 +92,9 @@ struct EnsLaunch {
 // Ensemble stage, all orders in one launch: npmax = largest member order + 1
 // (<= 8), wpb in {1, 2, 4}.
 hipError_t launch_ens_stage(int dtype, int npmax, int wpb, const EnsLaunch &a, hipStream_t s);
-// Ensemble stage over the members of one order np (items and bounds of that order).
-hipError_t launch_ens_stage_np(int dtype, int np, int wpb, const EnsLaunch &a, hipStream_t s);
+// Ensemble stage over the members of one order np and one stage-kernel layout
+// (0 line, 1 half; the items and bounds of that group).
+hipError_t launch_ens_stage_np(int dtype, int np, int layout, int wpb, const EnsLaunch &a, hipStream_t s);
 
 // Wavefronts (work items) of one member, and elements per wavefront.
 int waves_per_row(int np, int n_lon);

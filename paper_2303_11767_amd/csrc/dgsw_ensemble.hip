@@ -31,8 +31,9 @@ struct dg_ens {
   int *d_bounds = nullptr;
   int bounds_cap = 0;
   int wpb = 4, parts = 0, fused = 0, flat = 1;
-  // members of one order form one contiguous group of the sorted work list
-  struct Group { int np, begin, end, parts, bounds_off; double cost; };
+  std::vector<int> layout;               // per member: DG_KERNEL_LINE or DG_KERNEL_HALF
+  // members of one order and layout form one contiguous group of the sorted work list
+  struct Group { int np, lay, begin, end, parts, bounds_off; double cost; };
   std::vector<Group> groups;
   int graphs = 0;   // live dg_graph objects captured on this ensemble
   int freed = 0;    // dg_ens_free called while graphs were live: release deferred
@@ -58,6 +59,90 @@ void ens_release(dg_ens *e) {
   delete e;
 }
 
+// The work list: every member's wavefronts in its layout (row-major), sorted
+// by (order, layout), stable so members and rows keep their order; one group
+// per (order, layout); uploaded to the device.
+int build_items(dg_ens *e) {
+  std::vector<dgsw::EnsItem> items;
+  std::vector<double> cost;
+  std::vector<std::pair<int, int>> key;
+  for (int m = 0; m < e->n; ++m) {
+    const dg_ctx *c = e->members[m];
+    const int lay = e->layout[m];
+    dgsw::EnsItem it;
+    std::memset(&it, 0, sizeof(it));
+    it.glob = c->d_glob;
+    it.rows = c->d_rows;
+    it.off = e->off[m];
+    it.dt = e->dt.empty() ? 0.0 : e->dt[m];
+    it.n_lon = c->d.n_lon;
+    it.n_lat = c->d.n_lat;
+    it.np = c->np;
+    it.alpha_global = c->d.alpha_mode == DG_ALPHA_GLOBAL;
+    it.member = m;
+    const int n_lon = c->d.n_lon, n_lat = c->d.n_lat, E = c->E;
+    // cost ~ the work of one wavefront: elements per wavefront times the work
+    // per element (~np^3 per line of np lanes)
+    const double np3 = (double)c->np * c->np * c->np;
+    auto add = [&](int j, int seg, int e_end, double w) {
+      it.j = j;
+      it.seg = seg;
+      it.e_end = e_end;
+      items.push_back(it);
+      cost.push_back(w);
+      key.emplace_back(c->np, lay);
+    };
+    if (lay == DG_KERNEL_LINE) {
+      const int segs = dgsw::waves_per_row(c->np, n_lon);
+      for (int j = 0; j < n_lat; ++j)
+        for (int sg = 0; sg < segs; ++sg) add(j, sg, 0, np3);
+    } else {
+      const int gpw = 64 / (2 * c->np);
+      const double w = np3 * 0.5;
+      if (gpw <= n_lon && n_lon % gpw != 0) {      // packed across row ends
+        for (int e0 = 0; e0 < E; e0 += gpw) add(e0 / n_lon, e0, E, w);
+      } else {
+        const int segs = (n_lon + gpw - 1) / gpw;
+        for (int j = 0; j < n_lat; ++j)
+          for (int sg = 0; sg < segs; ++sg) add(j, j * n_lon + sg * gpw, (j + 1) * n_lon, w);
+      }
+    }
+  }
+  std::vector<int> idx(items.size());
+  for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return key[x] < key[y]; });
+  e->items.resize(items.size());
+  e->cost.resize(items.size());
+  for (size_t k = 0; k < idx.size(); ++k) {
+    e->items[k] = items[idx[k]];
+    e->cost[k] = cost[idx[k]];
+  }
+  e->groups.clear();
+  for (int k = 0; k < (int)e->items.size();) {
+    const std::pair<int, int> g0 = key[idx[k]];
+    dg_ens::Group g{g0.first, g0.second, k, k, 0, 0, 0.0};
+    while (k < (int)e->items.size() && key[idx[k]] == g0) g.cost += e->cost[k++];
+    g.end = k;
+    e->groups.push_back(g);
+  }
+  if (e->d_items) (void)hipFree(e->d_items);
+  e->d_items = nullptr;
+  hipError_t err;
+  if ((err = hipMalloc(reinterpret_cast<void **>(&e->d_items), e->items.size() * sizeof(dgsw::EnsItem))) !=
+      hipSuccess)
+    return fail(DG_ENOMEM, "hipMalloc of the ensemble work list");
+  if ((err = hipMemcpy(e->d_items, e->items.data(), e->items.size() * sizeof(dgsw::EnsItem),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(err, "upload of the ensemble work list");
+  return DG_OK;
+}
+
+bool all_line(const dg_ens *e) {
+  for (int l : e->layout)
+    if (l != DG_KERNEL_LINE) return false;
+  return true;
+}
+
 // Split items [begin, end) into `parts` contiguous ranges of about equal cost;
 // appends parts + 1 absolute item offsets to b.
 void balanced_ranges(const dg_ens *e, int begin, int end, int parts, std::vector<int> &b) {
@@ -81,6 +166,9 @@ void balanced_ranges(const dg_ens *e, int begin, int end, int parts, std::vector
 // cost-balanced range of the work list.  fused: one launch over all orders;
 // otherwise one launch per order with the workgroups shared out by cost.
 int upload_schedule(dg_ens *e, int wpb, int parts, int fused) {
+  if (fused && !all_line(e))
+    return fail(DG_EINVAL, "the single fused launch runs line-layout members only: "
+                           "set every order's layout to DG_KERNEL_LINE first (dg_ens_set_kernel)");
   // parts == 0: "flat", one workgroup per wpb consecutive items, scheduled by
   // the hardware like an ordinary grid
   const bool flat = parts == 0;
@@ -142,7 +230,7 @@ int ens_stage(dg_ens *e, const void *q, const void *q0, void *out, int combine, 
     a.flat = e->flat;
     a.begin = g.begin;
     a.end = g.end;
-    hipError_t err = dgsw::launch_ens_stage_np(e->dtype, g.np, e->wpb, a, s);
+    hipError_t err = dgsw::launch_ens_stage_np(e->dtype, g.np, g.lay, e->wpb, a, s);
     if (err != hipSuccess) return hip_fail(err, "ensemble stage launch");
   }
   return DG_OK;
@@ -193,64 +281,20 @@ int dg_ens_init(const dg_mesh_desc *members, int32_t n_members, void *hip_stream
     e->members.push_back(c);
     e->npmax = std::max(e->npmax, c->np);
     e->off[m + 1] = e->off[m] + (c->state_n + align - 1) / align * align;
-    // work items of this member in row-major wave order; cost ~ work per wavefront
-    const int segs = dgsw::waves_per_row(c->np, c->d.n_lon);
-    const double cost = (double)c->np * c->np * c->np;
-    for (int j = 0; j < c->d.n_lat; ++j)
-      for (int sg = 0; sg < segs; ++sg) {
-        dgsw::EnsItem it;
-        std::memset(&it, 0, sizeof(it));
-        it.glob = c->d_glob;
-        it.rows = c->d_rows;
-        it.off = e->off[m];
-        it.dt = 0.0;
-        it.n_lon = c->d.n_lon;
-        it.n_lat = c->d.n_lat;
-        it.np = c->np;
-        it.j = j;
-        it.seg = sg;
-        it.alpha_global = c->d.alpha_mode == DG_ALPHA_GLOBAL;
-        it.member = m;
-        e->items.push_back(it);
-        e->cost.push_back(cost);
-      }
+    // the member's layout as a single mesh of its size and order would take it
+    e->layout.push_back(c->kernel);
   }
   e->dt.assign(n_members, 0.0);
-  {
-    // sort the work list by order (stable: members and rows keep their order)
-    std::vector<int> idx(e->items.size());
-    for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
-    std::stable_sort(idx.begin(), idx.end(),
-                     [&](int x, int y) { return e->items[x].np < e->items[y].np; });
-    std::vector<dgsw::EnsItem> it2(idx.size());
-    std::vector<double> c2(idx.size());
-    for (size_t k = 0; k < idx.size(); ++k) {
-      it2[k] = e->items[idx[k]];
-      c2[k] = e->cost[idx[k]];
-    }
-    e->items.swap(it2);
-    e->cost.swap(c2);
-    for (int k = 0; k < (int)e->items.size();) {
-      const int np = e->items[k].np;
-      dg_ens::Group g{np, k, k, 0, 0, 0.0};
-      while (k < (int)e->items.size() && e->items[k].np == np) g.cost += e->cost[k++];
-      g.end = k;
-      e->groups.push_back(g);
-    }
-  }
   if (e->off[n_members] >= (int64_t(1) << 31)) {
     ens_release(e);
     return fail(DG_EINVAL, "packed ensemble state exceeds 2^31 values");
   }
-  hipError_t err;
-  if ((err = hipMalloc(reinterpret_cast<void **>(&e->d_items), e->items.size() * sizeof(dgsw::EnsItem))) != hipSuccess) {
-    ens_release(e);
-    return fail(DG_ENOMEM, "hipMalloc of the ensemble work list");
-  }
-  if ((err = hipMemcpy(e->d_items, e->items.data(), e->items.size() * sizeof(dgsw::EnsItem),
-                       hipMemcpyHostToDevice)) != hipSuccess) {
-    ens_release(e);
-    return hip_fail(err, "upload of the ensemble work list");
+  {
+    const int rc = build_items(e);
+    if (rc != DG_OK) {
+      ens_release(e);
+      return rc;
+    }
   }
   int rc = upload_schedule(e, 4, 0, 0);
   if (rc != DG_OK) {
@@ -351,6 +395,34 @@ int dg_ens_set_schedule(dg_ens *ens, int32_t waves_per_group, int32_t groups, in
   return upload_schedule(ens, waves_per_group, groups, fused);
 }
 
+int dg_ens_set_kernel(dg_ens *ens, int32_t order, int32_t kernel) {
+  if (!ens) return fail(DG_EINVAL, "ens is NULL");
+  if (kernel != DG_KERNEL_LINE && kernel != DG_KERNEL_HALF) return fail(DG_EINVAL, "unknown kernel");
+  if (ens->graphs > 0)
+    return fail(DG_EINVAL, "the work list is baked into live graphs of this ensemble: free them first");
+  bool any = false;
+  for (int m = 0; m < ens->n; ++m)
+    if (ens->members[m]->np == order + 1) any = true;
+  if (!any) return fail(DG_EINVAL, "no member of this order");
+  if (kernel != DG_KERNEL_LINE && ens->fused)
+    return fail(DG_EINVAL, "the single fused launch runs line-layout members only: choose a per-order schedule first");
+  for (int m = 0; m < ens->n; ++m)
+    if (ens->members[m]->np == order + 1) ens->layout[m] = kernel;
+  int rc = build_items(ens);
+  if (rc != DG_OK) return rc;
+  return upload_schedule(ens, ens->wpb, ens->flat ? 0 : ens->parts, ens->fused);
+}
+
+int dg_ens_get_kernel(const dg_ens *ens, int32_t order, int32_t *kernel) {
+  if (!ens || !kernel) return fail(DG_EINVAL, "NULL argument");
+  for (int m = 0; m < ens->n; ++m)
+    if (ens->members[m]->np == order + 1) {
+      *kernel = ens->layout[m];
+      return DG_OK;
+    }
+  return fail(DG_EINVAL, "no member of this order");
+}
+
 int dg_ens_get_schedule(const dg_ens *ens, int32_t *waves_per_group, int32_t *groups,
                         int32_t *fused) {
   if (!ens || !waves_per_group || !groups || !fused) return fail(DG_EINVAL, "NULL argument");
@@ -365,14 +437,30 @@ int dg_ens_autotune(dg_ens *ens, const void *q, void *work, const char *cache_pa
   if (ens->graphs > 0)
     return fail(DG_EINVAL, "the schedule is baked into live graphs of this ensemble: free them first");
   const std::string key = ens_key(ens);
+  std::vector<int> orders;
+  for (const dg_ctx *c : ens->members)
+    if (std::find(orders.begin(), orders.end(), c->np - 1) == orders.end()) orders.push_back(c->np - 1);
+  std::sort(orders.begin(), orders.end());
+  auto set_layouts = [&](const std::vector<int> &lay) -> int {
+    for (int m = 0; m < ens->n; ++m) ens->layout[m] = lay[ens->members[m]->np - 1];
+    return build_items(ens);
+  };
   if (cache_path) {
+    // line: key waves_per_group groups fused layout(order 0) .. layout(order 7)
     std::ifstream in(cache_path);
     std::string line;
     while (std::getline(in, line)) {
       std::istringstream ls(line);
       std::string k;
       int w = 0, p = 0, f = 0;
-      if (ls >> k >> w >> p >> f && k == key) return dg_ens_set_schedule(ens, w, p, f);
+      std::vector<int> lay(dgsw::kMaxNP, DG_KERNEL_LINE);
+      if (!(ls >> k >> w >> p >> f) || k != key) continue;
+      bool ok = true;
+      for (int o = 0; o < dgsw::kMaxNP && ok; ++o) ok = (bool)(ls >> lay[o]);
+      if (!ok) continue;
+      int rc = set_layouts(lay);
+      if (rc != DG_OK) return rc;
+      return dg_ens_set_schedule(ens, w, p, f);
     }
   }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -380,39 +468,75 @@ int dg_ens_autotune(dg_ens *ens, const void *q, void *work, const char *cache_pa
   char *w0 = static_cast<char *>(work);
   char *w1 = w0 + bytes;
   hipEvent_t a, b;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+  if (hipEventCreate(&a) != hipSuccess) return fail(DG_EHIP, "hipEventCreate");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
     return fail(DG_EHIP, "hipEventCreate");
-  const int n_items = (int)ens->items.size();
-  float best = 1e30f;
-  int best_w = ens->wpb, best_p = ens->parts, best_f = ens->fused;
+  }
   int rc = DG_OK;
-  for (int f : {0, 1}) {
-  for (int w : {1, 2, 4}) {
-    for (int p : {0, 256, 1024, 4096, 16384}) {
-      if (p * w > 4 * n_items && p > 256) continue;
-      if ((rc = upload_schedule(ens, w, p, f)) != DG_OK) break;
-      float t_best = 1e30f;
-      for (int rep = 0; rep < 4 && rc == DG_OK; ++rep) {
-        (void)hipEventRecord(a, s);
-        if ((rc = ens_stage(ens, q, nullptr, w0, 1, 0.0, 1.0, s)) != DG_OK) break;
-        if ((rc = ens_stage(ens, w0, q, w1, 1, 0.75, 0.25, s)) != DG_OK) break;
-        (void)hipEventRecord(b, s);
-        (void)hipEventSynchronize(b);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, a, b);
-        if (rep > 0) t_best = std::min(t_best, ms);   // first repetition warms up
-      }
-      if (rc != DG_OK) break;
-      if (t_best < best) {
-        best = t_best;
-        best_w = w;
-        best_p = p;
-        best_f = f;
+  // two stages on the caller's state (read only: q is input, work output),
+  // the best of three after a warm-up
+  auto time_two_stages = [&](float *out_ms) -> int {
+    float t_best = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {
+      (void)hipEventRecord(a, s);
+      int r = ens_stage(ens, q, nullptr, w0, 1, 0.0, 1.0, s);
+      if (r == DG_OK) r = ens_stage(ens, w0, q, w1, 1, 0.75, 0.25, s);
+      if (r != DG_OK) return r;
+      (void)hipEventRecord(b, s);
+      (void)hipEventSynchronize(b);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      if (rep > 0) t_best = std::min(t_best, ms);
+    }
+    *out_ms = t_best;
+    return DG_OK;
+  };
+  // 1. the layout of each order (flat per-order launches, 4 wavefronts per
+  //    workgroup), one order at a time with the others unchanged
+  std::vector<int> lay(dgsw::kMaxNP, DG_KERNEL_LINE);
+  for (int m = 0; m < ens->n; ++m) lay[ens->members[m]->np - 1] = ens->layout[m];
+  for (int o : orders) {
+    float best = 1e30f;
+    int best_l = lay[o];
+    for (int l : {DG_KERNEL_LINE, DG_KERNEL_HALF}) {
+      lay[o] = l;
+      float ms = 0.f;
+      if ((rc = set_layouts(lay)) != DG_OK || (rc = upload_schedule(ens, 4, 0, 0)) != DG_OK ||
+          (rc = time_two_stages(&ms)) != DG_OK)
+        break;
+      if (ms < best) {
+        best = ms;
+        best_l = l;
       }
     }
     if (rc != DG_OK) break;
+    lay[o] = best_l;
   }
-  if (rc != DG_OK) break;
+  if (rc == DG_OK) rc = set_layouts(lay);
+  // 2. the schedule: per-order or (line layouts only) one fused launch;
+  //    persistent with 256 .. 16384 cost-balanced workgroups, or flat; 1, 2
+  //    or 4 wavefronts per workgroup
+  const int n_items = (int)ens->items.size();
+  float best = 1e30f;
+  int best_w = 4, best_p = 0, best_f = 0;
+  for (int f : {0, 1}) {
+    if (rc != DG_OK) break;
+    if (f == 1 && !all_line(ens)) continue;
+    for (int w : {1, 2, 4}) {
+      if (rc != DG_OK) break;
+      for (int p : {0, 256, 1024, 4096, 16384}) {
+        if (p * w > 4 * n_items && p > 256) continue;
+        float ms = 0.f;
+        if ((rc = upload_schedule(ens, w, p, f)) != DG_OK || (rc = time_two_stages(&ms)) != DG_OK) break;
+        if (ms < best) {
+          best = ms;
+          best_w = w;
+          best_p = p;
+          best_f = f;
+        }
+      }
+    }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
@@ -420,7 +544,9 @@ int dg_ens_autotune(dg_ens *ens, const void *q, void *work, const char *cache_pa
   rc = upload_schedule(ens, best_w, best_p, best_f);
   if (rc == DG_OK && cache_path) {
     std::ofstream o(cache_path, std::ios::app);
-    o << key << " " << best_w << " " << best_p << " " << best_f << "\n";
+    o << key << " " << best_w << " " << best_p << " " << best_f;
+    for (int l : lay) o << " " << l;
+    o << "\n";
   }
   return rc;
 }

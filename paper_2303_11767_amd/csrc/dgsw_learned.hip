@@ -90,7 +90,7 @@ hipError_t forward(const float *P, const Weights &w, const __bf16 *Xb, int rows,
 struct TrainWs {
   Weights w;
   __bf16 *Xb, *H1, *H2, *dY, *dZ2, *dZ1;
-  float *Z1, *Z2, *Y, *dYf, *dZ2f, *dZ1f, *G1, *G2, *G3, *grad, *partial;
+  float *Z1, *Z2, *Y, *dYf, *dZ2f, *dZ1f, *G1, *G2, *G3, *grad, *partial, *split, *csum;
 };
 
 TrainWs carve_train(void *ws, int64_t rows, size_t *bytes) {
@@ -114,6 +114,8 @@ TrainWs carve_train(void *ws, int64_t rows, size_t *bytes) {
   t.G3 = c.take<float>((size_t)kHidden * kOutPad);
   t.grad = c.take<float>(kParams);
   t.partial = c.take<float>((rows * kOutPad + 255) / 256 + 1);
+  t.split = c.take<float>((size_t)dgsw::gemm_splits((int)rows) * kHidden * kHidden);
+  t.csum = c.take<float>((size_t)dgsw::colsum_chunks((int)rows) * kHidden);
   if (bytes) *bytes = c.off;
   return t;
 }
@@ -225,18 +227,18 @@ int dg_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t step,
   std::memset(&w, 0, sizeof(w));
   w.K = R;
   w.A = t.H2; w.lda = kHidden; w.M = kHidden; w.B = t.dY; w.ldb = kOutPad; w.N = kOutPad; w.C = t.G3; w.ldc = kOutPad;
-  if ((e = dgsw::launch_gemm(false, false, dgsw::kEpiPlain, w, s)) != hipSuccess) return hip_fail(e, "dW3");
+  if ((e = dgsw::launch_gemm_splitk(w, t.split, s)) != hipSuccess) return hip_fail(e, "dW3");
   w.A = t.H1; w.M = kHidden; w.B = t.dZ2; w.ldb = kHidden; w.N = kHidden; w.C = t.G2; w.ldc = kHidden;
-  if ((e = dgsw::launch_gemm(false, false, dgsw::kEpiPlain, w, s)) != hipSuccess) return hip_fail(e, "dW2");
+  if ((e = dgsw::launch_gemm_splitk(w, t.split, s)) != hipSuccess) return hip_fail(e, "dW2");
   w.A = t.Xb; w.lda = kInPad; w.M = kInPad; w.B = t.dZ1; w.C = t.G1;
-  if ((e = dgsw::launch_gemm(false, false, dgsw::kEpiPlain, w, s)) != hipSuccess) return hip_fail(e, "dW1");
+  if ((e = dgsw::launch_gemm_splitk(w, t.split, s)) != hipSuccess) return hip_fail(e, "dW1");
   float *gr = t.grad;
   if ((e = dgsw::launch_unpad(t.G1, kFeatures, kHidden, kHidden, gr + oW1, s)) != hipSuccess ||
-      (e = dgsw::launch_colsum(t.dZ1f, R, kHidden, kHidden, gr + ob1, s)) != hipSuccess ||
+      (e = dgsw::launch_colsum(t.dZ1f, R, kHidden, kHidden, t.csum, gr + ob1, s)) != hipSuccess ||
       (e = dgsw::launch_unpad(t.G2, kHidden, kHidden, kHidden, gr + oW2, s)) != hipSuccess ||
-      (e = dgsw::launch_colsum(t.dZ2f, R, kHidden, kHidden, gr + ob2, s)) != hipSuccess ||
+      (e = dgsw::launch_colsum(t.dZ2f, R, kHidden, kHidden, t.csum, gr + ob2, s)) != hipSuccess ||
       (e = dgsw::launch_unpad(t.G3, kHidden, kOut, kOutPad, gr + oW3, s)) != hipSuccess ||
-      (e = dgsw::launch_colsum(t.dYf, R, kOut, kOutPad, gr + ob3, s)) != hipSuccess)
+      (e = dgsw::launch_colsum(t.dYf, R, kOut, kOutPad, t.csum, gr + ob3, s)) != hipSuccess)
     return hip_fail(e, "gradients");
   if (grads && (e = hipMemcpyAsync(grads, gr, kParams * sizeof(float), hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(e, "gradient copy");

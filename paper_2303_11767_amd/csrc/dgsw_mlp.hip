@@ -21,22 +21,36 @@ namespace dgsw {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// erf by the rational approximation of Abramowitz & Stegun, formula 7.1.26
-// (Hastings): erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),
-// t = 1 / (1 + p x) for x >= 0, odd extension; absolute error <= 1.5e-7, far
-// below the BF16 rounding the activations then take.  Branch-free: one
-// hardware reciprocal and one hardware exponential.
-__device__ __forceinline__ float erf_as(float x) {
-  const float ax = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
-  const float poly =
-      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
-  const float r = fmaf(-poly, __expf(-ax * ax), 1.0f);
-  return copysignf(r, x);
+// GELU(z) = z Phi(z) = (z/2)(1 + erf(z / sqrt 2)) with erf from the rational
+// approximation of Abramowitz & Stegun, formula 7.1.26 (Hastings): for x >= 0,
+// erf(x) = 1 - P(t) exp(-x^2), t = 1 / (1 + p x),
+// P(t) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))), absolute error <= 1.5e-7,
+// far below the BF16 rounding the activations then take.  Since erf is odd,
+// z erf(z / sqrt 2) = |z| (1 - P exp(-z^2 / 2)), so
+//   GELU(z)  = max(z, 0) - |z| P / 2 exp(-z^2 / 2),
+//   GELU'(z) = Phi(z) + z phi(z) = [z >= 0] - sgn(z) P / 2 e + z e / sqrt(2 pi),
+// e = exp(-z^2 / 2): branch-free, one hardware reciprocal and one hardware
+// base-2 exponential each.  The A&S coefficients enter halved (P / 2) and p
+// is scaled by 1 / sqrt 2 (t from |z| directly).
+namespace gelu_as {
+constexpr float kP = 0.3275911f * 0.70710678118654752f;
+constexpr float kA1 = 0.5f * 0.254829592f, kA2 = 0.5f * -0.284496736f, kA3 = 0.5f * 1.421413741f,
+                kA4 = 0.5f * -1.453152027f, kA5 = 0.5f * 1.061405429f;
+constexpr float kHalfLog2e = 0.72134752044448170f;   // log2(e) / 2: exp(-z^2/2) = 2^(-z^2 log2(e)/2)
+__device__ __forceinline__ float half_poly(float az) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(kP, az, 1.0f));
+  return t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, kA5, kA4), kA3), kA2), kA1);
 }
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gauss(float z) { return __builtin_amdgcn_exp2f(-(z * z) * kHalfLog2e); }
+}  // namespace gelu_as
+
+__device__ __forceinline__ float gelu_f(float z) {
+  const float az = fabsf(z);
+  return fmaf(-az * gelu_as::half_poly(az), gelu_as::gauss(z), fmaxf(z, 0.0f));
+}
 __device__ __forceinline__ float gelu_grad_f(float z) {
-  return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+  const float hp = gelu_as::half_poly(fabsf(z));
+  return fmaf(gelu_as::gauss(z), fmaf(z, 0.39894228040143268f, -copysignf(hp, z)), z >= 0.0f ? 1.0f : 0.0f);
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -56,6 +70,11 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, cons
   const int m0 = blockIdx.x * 64 + (wv >> 1) * 32;
   const int n0 = blockIdx.y * 64 + (wv & 1) * 32;
   if (n0 >= N) return;
+  // split K: workgroup z sums k in [z kc, min(K, (z + 1) kc)) into the z-th
+  // partial product C + z M ldc (gridDim.z == 1: the whole K into C)
+  const int kc = gridDim.z == 1 ? K : ((K / 32 + gridDim.z - 1) / gridDim.z) * 32;
+  const int kb = blockIdx.z * kc, ke = kb + kc < K ? kb + kc : K;
+  if (gridDim.z > 1) C = static_cast<float *>(C) + (size_t)blockIdx.z * M * ldc;
   const int r = lane & 15, kq = (lane >> 4) * 8;
   f32x4 acc[2][2];
 #pragma unroll
@@ -69,7 +88,7 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, cons
     ma[i] = m < M ? m : M - 1;
     nb[i] = n0 + 16 * i + r;
   }
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  for (int k0 = kb; k0 < ke; k0 += 32) {
     bf16x8 a[2], b[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -125,6 +144,37 @@ static hipError_t gemm_t(const GemmArgs &g, hipStream_t s) {
   dim3 grid((g.M + 63) / 64, (g.N + 63) / 64);
   hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI>), grid, dim3(256), 0, s, g.A, g.B, g.M, g.N, g.K, g.lda,
                      g.ldb, g.bias, g.Zin, g.Zout, g.C, g.ldc);
+  return hipGetLastError();
+}
+
+// Sum of nsplit partial products part[z][n] over z in order (deterministic).
+__global__ void k_sum_split(const float *__restrict__ part, int nsplit, int n, float *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = 0.f;
+  for (int z = 0; z < nsplit; ++z) acc += part[(size_t)z * n + i];
+  out[i] = acc;
+}
+
+int gemm_splits(int K) {
+  const int s = (K + 255) / 256;
+  return s < 1 ? 1 : (s > kMaxSplits ? kMaxSplits : s);
+}
+
+hipError_t launch_gemm_splitk(const GemmArgs &g, float *partial, hipStream_t s) {
+  if (g.M <= 0) return hipSuccess;
+  if (g.K % 32 || g.N % 32) return hipErrorInvalidValue;
+  const int z = gemm_splits(g.K);
+  GemmArgs p = g;
+  p.C = partial;
+  dim3 grid((g.M + 63) / 64, (g.N + 63) / 64, z);
+  hipLaunchKernelGGL((k_gemm<false, false, kEpiPlain>), grid, dim3(256), 0, s, p.A, p.B, p.M, p.N, p.K, p.lda,
+                     p.ldb, p.bias, p.Zin, p.Zout, p.C, p.ldc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int n = g.M * g.ldc;
+  hipLaunchKernelGGL(k_sum_split, dim3((n + 255) / 256), dim3(256), 0, s, partial, z, n,
+                     static_cast<float *>(g.C));
   return hipGetLastError();
 }
 
@@ -475,18 +525,36 @@ hipError_t launch_mse_grad(const float *Y, const float *T, unsigned mask_bits, i
   return hipGetLastError();
 }
 
-// Column sums of G[rows][ld] for the first n columns (bias gradients), one
-// thread per column, rows in order (deterministic).
-__global__ void k_colsum(const float *__restrict__ G, int rows, int n, int ld, float *__restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
+// Column sums of G[rows][ld] for the first n columns (bias gradients) in two
+// deterministic passes: workgroup (column block, chunk) sums its chunk of
+// rows for 64 columns (4 row lanes per column, then a fixed tree), and
+// k_sum_split adds the chunks in order.
+__global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ G, int rows, int n, int ld,
+                                                     int chunk, float *__restrict__ part) {
+  __shared__ float sh[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), rl = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * chunk, r1 = r0 + chunk < rows ? r0 + chunk : rows;
   float acc = 0.f;
-  for (int m = 0; m < rows; ++m) acc += G[(size_t)m * ld + c];
-  out[c] = acc;
+  if (c < n)
+    for (int m = r0 + rl; m < r1; m += 4) acc += G[(size_t)m * ld + c];
+  sh[rl][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (rl == 0 && c < n)
+    part[(size_t)blockIdx.y * n + c] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
 }
 
-hipError_t launch_colsum(const float *G, int rows, int n, int ld, float *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3((n + 63) / 64), dim3(64), 0, s, G, rows, n, ld, out);
+int colsum_chunks(int rows) {
+  const int c = (rows + 63) / 64;
+  return c < 1 ? 1 : (c > kMaxColChunks ? kMaxColChunks : c);
+}
+
+hipError_t launch_colsum(const float *G, int rows, int n, int ld, float *part, float *out, hipStream_t s) {
+  const int chunks = colsum_chunks(rows);
+  const int chunk = (rows + chunks - 1) / chunks;
+  hipLaunchKernelGGL(k_colsum_part, dim3((n + 63) / 64, chunks), dim3(256), 0, s, G, rows, n, ld, chunk, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_split, dim3((n + 255) / 256), dim3(256), 0, s, part, chunks, n, out);
   return hipGetLastError();
 }
 

@@ -23,6 +23,12 @@ struct GemmArgs {
   int ldc;
 };
 hipError_t launch_gemm(bool a_kc, bool b_kc, int epi, const GemmArgs &g, hipStream_t s);
+// Weight gradients C[M][N] = sum over k < K of A[k][m] B[k][n] (both operands
+// row-major over k): K split into gemm_splits(K) ranges of workgroups, the
+// partial products (partial: gemm_splits(K) * M * ldc floats) summed in order.
+constexpr int kMaxSplits = 64;
+int gemm_splits(int K);
+hipError_t launch_gemm_splitk(const GemmArgs &g, float *partial, hipStream_t s);
 // The learned stage's correction step, fused into the network kernel.
 struct CorrectionArgs {
   const void *L1;                // plain r = 1 right-hand side [E][12] (state dtype)
@@ -48,7 +54,10 @@ hipError_t launch_prep_weights(const float *W, int k_in, int n_out, int kp, int 
                                hipStream_t s);
 hipError_t launch_mse_grad(const float *Y, const float *T, unsigned mask_bits, int rows, int n_out, int ld,
                            float scale, __bf16 *dY, float *dYf, float *partial, int *nblocks, hipStream_t s);
-hipError_t launch_colsum(const float *G, int rows, int n, int ld, float *out, hipStream_t s);
+// column sums over rows (partial: colsum_chunks(rows) * n floats)
+constexpr int kMaxColChunks = 256;
+int colsum_chunks(int rows);
+hipError_t launch_colsum(const float *G, int rows, int n, int ld, float *part, float *out, hipStream_t s);
 hipError_t launch_sum(const float *p, int n, float scale, float *out, hipStream_t s);
 hipError_t launch_to_bf16(const float *X, int rows, int n, int ldx, __bf16 *Xb, hipStream_t s);
 hipError_t launch_pad(const float *b, int n, int np_, float *out, hipStream_t s);

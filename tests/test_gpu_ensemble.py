@@ -101,9 +101,17 @@ def test_ensemble_steps_equal_plain_steps(dg, dtype):
         assert err <= (1e-13 if dtype == "f64" else 1e-6)
 
 
+ORDERS = sorted({m["order"] for m in MEMBERS})
+
+
 def test_schedule_does_not_change_results(dg):
+    """With every member in the line layout (the fused launch runs that layout
+    only): per-order and fused schedules of any shape give bitwise the same
+    stage."""
     say("schedules")
     ens, q, dts = build(dg, "f32")
+    for o in ORDERS:
+        ens.set_kernel(o, "line")
     ref = ens.empty_state()
     ens.rk_stage(q, None, ref, 0.0, 1.0)
     for w, g, f in [(1, 1, 0), (1, 7, 1), (2, 64, 0), (4, 3, 1), (4, 1000, 0), (2, 100000, 1), (4, 0, 0), (2, 0, 1)]:
@@ -113,15 +121,61 @@ def test_schedule_does_not_change_results(dg):
         assert torch.equal(out, ref), (w, g)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_layouts_per_order_match_plain_members(dg, dtype):
+    """Every order of the ensemble in each stage-kernel layout: one batched
+    stage equals each member's own stage in the same layout (to roundoff; the
+    same arithmetic), under per-order flat and persistent schedules; the
+    fused launch refuses other layouts than the line one."""
+    say("ensemble layouts", dtype)
+    ens, q, dts = build(dg, dtype)
+    for lay in ("line", "half"):
+        for o in ORDERS:
+            ens.set_kernel(o, lay)
+            assert ens.kernel(o) == lay
+            for sched in ((4, 0, 0), (2, 300, 0)):
+                ens.set_schedule(*sched)
+                out = ens.empty_state()
+                ens.rk_stage(q, None, out, 0.0, 1.0)
+                for k, (m, qv, ov) in enumerate(zip(ens.members, ens.views(q), ens.views(out))):
+                    m.kernel = ens.kernel(m.order)
+                    ref = torch.empty_like(qv)
+                    m.rk_stage(qv.contiguous(), None, ref, 0.0, 1.0, dts[k])
+                    err = (ov.double() - ref.double()).abs().max().item() / ref.double().abs().max().item()
+                    assert err <= (1e-14 if dtype == "f64" else 1e-6), (lay, o, sched, k, err)
+            if lay != "line":
+                with pytest.raises(dg.DGError) as ei:
+                    ens.set_schedule(4, 0, 1)
+                assert ei.value.code == dg._lib.DG_EINVAL
+            ens.set_kernel(o, "line")
+    with pytest.raises(dg.DGError):
+        ens.set_kernel(6, "half")          # no member of order 6
+
+
 def test_autotune_and_cache(dg, tmp_path):
     say("autotune")
     ens, q, dts = build(dg, "f32")
     path = str(tmp_path / "tune.txt")
     w, g, f = ens.autotune(q, ens.empty_work(), path)
-    assert w in (1, 2, 4) and g >= 1
-    assert os.path.exists(path) and len(open(path).read().split()) == 4
-    ens.set_schedule(1, 1, not f)
+    lays = {o: ens.kernel(o) for o in ORDERS}
+    say("  chosen", (w, g, f), lays)
+    assert w in (1, 2, 4) and g >= 0          # 0: flat, one workgroup per w items
+    # one line: key, the schedule and one layout per order 0..7
+    assert os.path.exists(path) and len(open(path).read().split()) == 4 + 8
+    for o in ORDERS:
+        ens.set_kernel(o, "line")
+    ens.set_schedule(1, 1, not f if all(v == "line" for v in lays.values()) else 0)
     assert ens.autotune(q, ens.empty_work(), path) == (w, g, f)
+    assert {o: ens.kernel(o) for o in ORDERS} == lays
+    # the tuned configuration still computes the members' own stages
+    out = ens.empty_state()
+    ens.rk_stage(q, None, out, 0.0, 1.0)
+    for k, (m, qv, ov) in enumerate(zip(ens.members, ens.views(q), ens.views(out))):
+        m.kernel = ens.kernel(m.order)
+        ref = torch.empty_like(qv)
+        m.rk_stage(qv.contiguous(), None, ref, 0.0, 1.0, dts[k])
+        err = (ov.double() - ref.double()).abs().max().item() / ref.double().abs().max().item()
+        assert err <= 1e-6, (k, err)
 
 
 def test_graph_replays_match_eager(dg):

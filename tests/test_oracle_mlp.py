@@ -123,3 +123,41 @@ def test_projection_reproduces_lower_order_and_conserves_mass():
     q4r, _ = band_limited_state(n_lon, n_lat, 4, 6, 5)
     p1 = project_order(q4r, m4, m1)
     np.testing.assert_allclose(m1.mass(p1), m4.mass(q4r), rtol=1e-12)
+
+
+@pytest.mark.parametrize("src,dst", [(4, 0), (4, 2), (5, 3), (3, 2)])
+def test_projection_any_order_is_the_cos_weighted_orthogonal_projection(src, dst):
+    """project_order onto orders other than 1 (the plain runs of the
+    equal-error comparison start from it): a field already of the target
+    degree is returned; the residual q - P q is orthogonal, in the
+    cos-weighted inner product of the mass matrix, to every target basis
+    function (checked with the source's own mass matrix, a different
+    computation); projections nest, P_k P_m = P_k for k < m; mass is kept."""
+    n_lon, n_lat = 10, 5
+    ms, md = SphereDG(n_lon, n_lat, src), SphereDG(n_lon, n_lat, dst)
+    ns, nd = src + 1, dst + 1
+
+    def embed(q, n_lo, n_hi):
+        out = np.zeros((q.shape[0], 3, n_hi * n_hi))
+        for b in range(n_lo):
+            out[:, :, b * n_hi:b * n_hi + n_lo] = q[:, :, b * n_lo:(b + 1) * n_lo]
+        return out
+
+    qd, _ = band_limited_state(n_lon, n_lat, dst, 4, 8)
+    np.testing.assert_allclose(project_order(embed(qd, nd, ns), ms, md), qd, rtol=0,
+                               atol=1e-10 * np.abs(qd).max())
+    q, _ = band_limited_state(n_lon, n_lat, src, 6, 9)
+    p = project_order(q, ms, md)
+    r = ms.grid(q - embed(p, nd, ns))                       # residual in the source basis
+    for b in range(nd):
+        for a in range(nd):
+            # <phi_(a,b), r>_M: row (b, a) of the source mass matrix against r
+            row = b * ns + a
+            ip = np.einsum("jn,jivn->jiv", ms.M[:, row, :], r)
+            assert np.abs(ip).max() <= 1e-10 * np.abs(np.einsum("jn,jivn->jiv", np.abs(ms.M[:, row, :]),
+                                                                 np.abs(ms.grid(q)))).max()
+    if dst > 0:
+        mid = SphereDG(n_lon, n_lat, dst - 1)
+        np.testing.assert_allclose(project_order(p, md, mid), project_order(q, ms, mid), rtol=0,
+                                   atol=1e-10 * np.abs(q).max())
+    np.testing.assert_allclose(md.mass(p), ms.mass(q), rtol=1e-12)
