@@ -96,13 +96,15 @@ int make_ctx(const dg_mesh_desc *desc, const dgsw::HostTables &t, hipStream_t s,
   // kernel layout, chosen from MI355X stage timings of both layouts: the
   // half-line layout where the line layout leaves the GPU latency-bound (at
   // most 2048 wavefronts, about two per SIMD), for FP64 at r >= 5, where the
-  // line layout's registers allow only one wavefront per SIMD, and for FP64
-  // at r = 3, where it holds four wavefronts per SIMD against the line
-  // layout's two; the line layout otherwise (dg_autotune measures instead)
+  // line layout's registers allow only one wavefront per SIMD, for FP64 at
+  // r = 3, where it holds four wavefronts per SIMD against the line layout's
+  // two, and for FP64 at r = 1 (360 x 180: 10.8 against 13.1 us per stage);
+  // the line layout otherwise (dg_autotune measures instead)
   {
     const int waves_line = dgsw::waves_per_row(desc->order + 1, desc->n_lon) * desc->n_lat;
-    const bool half = (desc->dtype == DG_F64 && (desc->order >= 5 || desc->order == 3)) ||
-                      waves_line <= 2048;
+    const bool half =
+        (desc->dtype == DG_F64 && (desc->order >= 5 || desc->order == 3 || desc->order == 1)) ||
+        waves_line <= 2048;
     c->kernel = half ? DG_KERNEL_HALF : DG_KERNEL_LINE;
   }
   c->np = desc->order + 1;

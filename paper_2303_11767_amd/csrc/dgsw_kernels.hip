@@ -6,13 +6,13 @@ namespace dgsw {
 
 // PK: wavefront w of a layer takes the GPW consecutive elements from w GPW on,
 // across row ends (needs GPW <= n_lon; ceil(E / GPW) wavefronts); otherwise
-// row-aligned segments, segs per row.  One wavefront per workgroup (its LDS
-// then fits 15 wavefronts per CU at FP64 r = 3).  Register budget: four
-// wavefronts per SIMD (128 registers) at FP64 r = 3 with the one-state
-// combinations, where the kernel needs 130-138 and the last few cost nothing
-// measurable (the RK4 combination would spill); two (256) elsewhere, which
-// keeps the FP64 r >= 5 cases, at the edge of 256, from spilling into
-// accumulation registers and halving their occupancy.
+// row-aligned segments, segs per row.  One wavefront per workgroup (8960
+// bytes of LDS at FP64 r = 3: the 16 wavefronts per CU that the registers
+// allow fit).  Register budget: four wavefronts per SIMD (128 registers) at
+// FP64 r = 3 with the one-state combinations, which fit without spilling (the
+// RK4 combination would spill); two (256) elsewhere, which keeps the FP64
+// r >= 5 cases, at the edge of 256, from spilling into accumulation registers
+// and halving their occupancy.
 template <typename T, int NP, int CM>
 struct H2Occ {
   static constexpr int value = sizeof(T) == 8 && NP == 4 && CM != 2 ? 4 : 2;
@@ -24,7 +24,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(H2Occ<T, NP, CM>::value))) __launc
   using S_ = ShapeH2<T, NP>;
   __shared__ T tab_all[WPB][S_::TB];
   __shared__ T sh_all[WPB][S_::SLOTS * S_::SH];
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wv = WPB == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int blk = xcd_block(blockIdx.x, gridDim.x) * WPB + wv;
   const int E = A.n_lon * A.n_lat;
   const int per = PK ? (E + S_::GPW - 1) / S_::GPW : segs * A.n_lat;   // wavefronts of one layer

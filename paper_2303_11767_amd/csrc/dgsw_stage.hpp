@@ -75,7 +75,7 @@ struct Shape {
 
 // Reciprocal and square root from the hardware approximations.  FP64: v_rcp_f64
 // refined by two Newton steps, and v_rsq_f64 refined by a Goldschmidt step (both
-// within about 1 ulp for the normal, positive depths used here); FP32: v_rcp_f32
+// within an ulp or two for the normal, positive depths used here); FP32: v_rcp_f32
 // and v_sqrt_f32 (1 ulp).  The square root only enters the Rusanov speed estimate.
 template <typename T>
 __device__ __forceinline__ T dg_rcp(T x);
@@ -94,15 +94,14 @@ template <typename T>
 __device__ __forceinline__ T dg_sqrt(T x);
 template <>
 __device__ __forceinline__ double dg_sqrt<double>(double x) {
-  // Goldschmidt iteration from the hardware reciprocal square root (about 29
-  // correct bits): g -> sqrt(x), h -> 1/(2 sqrt(x)), then one residual correction.
-  double y = __builtin_amdgcn_rsq(x);
-  double g = x * y, h = 0.5 * y;
-  double r = __builtin_fma(-g, h, 0.5);
-  g = __builtin_fma(g, r, g);
-  h = __builtin_fma(h, r, h);
-  const double d = __builtin_fma(-g, g, x);
-  return __builtin_fma(d, h, g);
+  // One Goldschmidt step from the hardware reciprocal square root (about 29
+  // correct bits): with g = x y and h = y / 2, r = 1/2 - g h and g + g r has a
+  // relative error of about 3/2 of the square of y's, i.e. within an ulp or two;
+  // enough for the wave-speed estimate, the only use of this square root.
+  const double y = __builtin_amdgcn_rsq(x);
+  const double g = x * y;
+  const double r = __builtin_fma(-g, 0.5 * y, 0.5);
+  return __builtin_fma(g, r, g);
 }
 template <>
 __device__ __forceinline__ float dg_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -155,16 +154,20 @@ struct Side {
 };
 
 // Rusanov bracket on a constant-longitude edge, without the 1/R factor:
-// (f(q-) + f(q+))/2 - alpha/2 (q+ - q-), f = (hu, hu u + p, hu v).
+// (f(q-) + f(q+))/2 - alpha/2 (q+ - q-), f = (hu, hu u + p, hu v).  The
+// bracket is symmetric in its two states except for the jump, so the caller
+// may pass them in either order: sgn = 1 for (q-, q+), -1 for (q+, q-) (the
+// result is the same to the last bit: only signs change).
 template <typename T>
 __device__ __forceinline__ void rusanov_lambda(const T qm[3], const T qp[3], T H, T g,
-                                               bool fixed, T alpha_fixed, T out[3]) {
+                                               bool fixed, T alpha_fixed, T out[3], T sgn = T(1)) {
   const Side<T> m(qm, H, g), p(qp, H, g);
   T a = alpha_fixed;
   if (!fixed) {
     const T sm = fabs(m.u) + m.c, sp = fabs(p.u) + p.c;
     a = sm > sp ? sm : sp;
   }
+  a *= sgn;
   out[0] = T(0.5) * (qm[1] + qp[1]) - T(0.5) * a * (qp[0] - qm[0]);
   out[1] = T(0.5) * ((qm[1] * m.u + m.p) + (qp[1] * p.u + p.p)) - T(0.5) * a * (qp[1] - qm[1]);
   out[2] = T(0.5) * (qm[1] * m.v + qp[1] * p.v) - T(0.5) * a * (qp[2] - qm[2]);
@@ -174,13 +177,14 @@ __device__ __forceinline__ void rusanov_lambda(const T qm[3], const T qp[3], T H
 // the cos(theta_edge)/R factor.
 template <typename T>
 __device__ __forceinline__ void rusanov_theta(const T qm[3], const T qp[3], T H, T g,
-                                              bool fixed, T alpha_fixed, T out[3]) {
+                                              bool fixed, T alpha_fixed, T out[3], T sgn = T(1)) {
   const Side<T> m(qm, H, g), p(qp, H, g);
   T a = alpha_fixed;
   if (!fixed) {
     const T sm = fabs(m.v) + m.c, sp = fabs(p.v) + p.c;
     a = sm > sp ? sm : sp;
   }
+  a *= sgn;
   out[0] = T(0.5) * (qm[2] + qp[2]) - T(0.5) * a * (qp[0] - qm[0]);
   out[1] = T(0.5) * (qm[2] * m.u + qp[2] * p.u) - T(0.5) * a * (qp[1] - qm[1]);
   out[2] = T(0.5) * ((qm[2] * m.v + m.p) + (qp[2] * p.v + p.p)) - T(0.5) * a * (qp[2] - qm[2]);
@@ -525,10 +529,17 @@ struct ShapeH2 {
   static constexpr int K0 = (NP + 1) / 2;
   static constexpr int NB = 3 * (NP + 2) * NP;
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
-  // second phase: the volume outputs [3][2][NP][NP], then the longitude and
-  // latitude edge fluxes of both halves [3][2][NP] each
-  static constexpr int oFX = 6 * NP * NP, oGY = oFX + 6 * NP;
-  static constexpr int SH = cmax(NB + 12 * NP, oGY + 6 * NP);
+  // SPLIT: each half evaluates the node terms at its own NP / 2 nodes of a
+  // column and hands them to the other half (FP64 with an even r + 1 >= 4)
+  static constexpr bool SPLIT = sizeof(T) == 8 && NP % 2 == 0 && NP >= 4;
+  // second phase: the volume outputs [3][2][NP][NP], the longitude edge
+  // fluxes of both halves [3][2][NP], and the latitude ones [3][2][NP] (oGY).
+  // With SPLIT the latitude ones and then the node terms, XQ quantities
+  // [XQ][NP][NP] at a time, use the region of the volume outputs first (both
+  // are read before those are written), which keeps FP64 r = 3 within the LDS
+  // of 16 wavefronts per CU.
+  static constexpr int oFX = 6 * NP * NP, oGY = SPLIT ? 0 : oFX + 6 * NP, XQ = 4;
+  static constexpr int SH = cmax(NB + 12 * NP, oFX + (SPLIT ? 6 : 12) * NP);
   static constexpr int SLOTS = GPW + (SPARE ? 1 : 0);
   // LDS copy of the tables: the GlobTab prefix (B, D, Pp, Pm, w), then the
   // whole RowTab of the wavefront's first row and of the row after it (a
@@ -588,6 +599,11 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
                                               const int e_end, const int lane, T *tab, T *sh) {
   using S_ = ShapeH2<T, NP>;
   constexpr int N = S_::N, GPW = S_::GPW, SH = S_::SH, NB = S_::NB, K0 = S_::K0;
+  // SPLIT: each half evaluates the node terms at its own K0 nodes of the
+  // column and takes the other half's through LDS (FP64 with an even r + 1 >= 4,
+  // where the node terms dominate and it measured faster); otherwise both
+  // halves evaluate all r + 1 nodes (faster at r = 2 and 4 and in FP32)
+  constexpr bool SPLIT = S_::SPLIT;
   static_assert(sizeof(GlobTab<T, NP>) >= sizeof(T) * S_::G1, "GlobTab prefix");
   using RT_ = RowTab<T, NP>;
   static_assert(offsetof(RT_, MS) == sizeof(T) * S_::rMS, "RowTab layout");
@@ -606,7 +622,9 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
   const int h = r >= NP ? 1 : 0;
   const int t = r - h * NP;
   const int e_raw = e0 + g;
-  const bool active = !idle && e_raw < e_end;
+  // lanes that store, as a wavefront mask (scalar registers: nothing per lane
+  // stays live until the stores)
+  const unsigned long long store_mask = __builtin_amdgcn_ballot_w64(!idle && e_raw < e_end);
   const int e = e_raw < e_end ? e_raw : e_end - 1;      // tail lanes work on a valid element
   const int rsel = PK && e >= (j0 + 1) * n_lon ? 1 : 0;  // 1: the element is in row j0 + 1
   const int j = j0 + rsel;
@@ -655,19 +673,37 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
       tab[k] = k < S_::G1 ? g0[k] : (k < S_::G1 + S_::RP ? ra[k - S_::G1] : rb[k - S_::G1 - S_::RP]);
   }
   // per-lane coefficients: rows h K0 + k of B (clamped), this half's own edge
-  // (h = 0: +1, h = 1: -1) and the facing edge of its neighbours
+  // (h = 0: +1, h = 1: -1) and the facing edge of its neighbours; from the
+  // LDS tables where the registers are tight (SPLIT), else selected from the
+  // scalar-loaded tables
   T BP[K0][NP], PE[NP], PF[NP];
+  if (SPLIT) {
+    wave_sync();
 #pragma unroll
-  for (int k = 0; k < K0; ++k)
+    for (int k = 0; k < K0; ++k) {
+      const int p = h * K0 + k < NP ? h * K0 + k : NP - 1;
+#pragma unroll
+      for (int a = 0; a < NP; ++a) BP[k][a] = tab[S_::oB + p * NP + a];
+    }
+    const int oE = h ? S_::oPm : S_::oPp, oF = h ? S_::oPp : S_::oPm;
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-      const int p1 = K0 + k < NP ? K0 + k : NP - 1;
-      BP[k][a] = h ? gt->B[p1][a] : gt->B[k][a];
+      PE[a] = tab[oE + a];
+      PF[a] = tab[oF + a];
     }
+  } else {
 #pragma unroll
-  for (int a = 0; a < NP; ++a) {
-    PE[a] = h ? gt->Pm[a] : gt->Pp[a];
-    PF[a] = h ? gt->Pp[a] : gt->Pm[a];
+    for (int k = 0; k < K0; ++k)
+#pragma unroll
+      for (int a = 0; a < NP; ++a) {
+        const int p1 = K0 + k < NP ? K0 + k : NP - 1;
+        BP[k][a] = h ? gt->B[p1][a] : gt->B[k][a];
+      }
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      PE[a] = h ? gt->Pm[a] : gt->Pp[a];
+      PF[a] = h ? gt->Pp[a] : gt->Pm[a];
+    }
   }
 
   // ---- xi pass: A[v][p][b=t] for this half's p, the own edge row, the
@@ -703,23 +739,31 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
   }
   wave_sync();
 
-  // ---- eta pass: nodal values of column p = t at all its nodes s, own and
-  // neighbour traces of this half's two edges
-  T nd[3][NP], trX[3], trY[3], nbX[3], nbY[3];
-  T bt[NP];
+  // ---- eta pass: nodal values of column p = t at the nodes s this lane
+  // evaluates (SPLIT: this half's s = h K0 + k, clamped like the xi pass's
+  // rows; else all s), own and neighbour traces of this half's two edges
+  constexpr int NDN = SPLIT ? K0 : NP;
+  T nd[3][NDN], trX[3], trY[3], nbX[3], nbY[3];
+  T bt[NP], Bs[NDN][NP];
 #pragma unroll
   for (int k = 0; k < NP; ++k) bt[k] = tab[S_::oB + t * NP + k];          // P~_k(xi_t)
+#pragma unroll
+  for (int k = 0; k < NDN; ++k) {
+    const int sk = !SPLIT ? k : (h * K0 + k < NP ? h * K0 + k : NP - 1);
+#pragma unroll
+    for (int b = 0; b < NP; ++b) Bs[k][b] = SPLIT ? tab[S_::oB + sk * NP + b] : gt->B[k][b];  // P~_b(eta_s)
+  }
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
     T col[NP];
 #pragma unroll
     for (int b = 0; b < NP; ++b) col[b] = S[(v * (NP + 2) + t) * NP + b];
 #pragma unroll
-    for (int s = 0; s < NP; ++s) {
+    for (int k = 0; k < NDN; ++k) {
       T acc = T(0);
 #pragma unroll
-      for (int b = 0; b < NP; ++b) acc += col[b] * gt->B[s][b];
-      nd[v][s] = acc;
+      for (int b = 0; b < NP; ++b) acc += col[b] * Bs[k][b];
+      nd[v][k] = acc;
     }
     T ay = T(0), ax = T(0), nx = T(0), ny = T(0);
 #pragma unroll
@@ -734,16 +778,13 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
   wave_sync();
 
   // ---- Rusanov fluxes at edge node t of this half's two edges (minus side =
-  // west / south: the own trace for h = 0, the neighbour's for h = 1)
+  // west / south: the own trace for h = 0, the neighbour's for h = 1; the
+  // states go in as (own, neighbour) with the jump's sign set by h)
   T FhX[3], GhY[3];
   {
-    T qm[3], qp[3];
-#pragma unroll
-    for (int v = 0; v < 3; ++v) { qm[v] = h ? nbX[v] : trX[v]; qp[v] = h ? trX[v] : nbX[v]; }
-    rusanov_lambda<T>(qm, qp, H, grav, fixed, alpha, FhX);
-#pragma unroll
-    for (int v = 0; v < 3; ++v) { qm[v] = h ? nbY[v] : trY[v]; qp[v] = h ? trY[v] : nbY[v]; }
-    rusanov_theta<T>(qm, qp, H, grav, fixed, alpha, GhY);
+    const T sgn = h ? T(-1) : T(1);
+    rusanov_lambda<T>(trX, nbX, H, grav, fixed, alpha, FhX, sgn);
+    rusanov_theta<T>(trY, nbY, H, grav, fixed, alpha, GhY, sgn);
   }
   const T fY = tab[ro + (h ? S_::rBot : S_::rTop)] * invR;     // 0 at a pole edge
 #pragma unroll
@@ -761,9 +802,12 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
     GhN[v] = h ? other : GhY[v];
     GhS[v] = h ? GhY[v] : other;
   }
+  if (SPLIT) wave_sync();   // the node terms below reuse the region of oGY
 
-  // ---- volume: fluxes and sources at all nodes (t, s) of column t,
-  // contracted over s for this half's outputs b = h K0 + kb
+  // ---- volume: fluxes and sources at the nodes (t, s) of column t,
+  // contracted over s for this half's outputs b = h K0 + kb.  SPLIT: this
+  // lane evaluates its half's nodes and the other half's arrive through LDS,
+  // XQ of the eight node terms at a time; else it evaluates all s.
   T ZD[3][K0], ZG[3][K0], ZS[2][K0];
 #pragma unroll
   for (int v = 0; v < 3; ++v)
@@ -776,25 +820,73 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
   int bh[K0];
 #pragma unroll
   for (int kb = 0; kb < K0; ++kb) bh[kb] = h * K0 + kb < NP ? h * K0 + kb : NP - 1;
-#pragma unroll
-  for (int s = 0; s < NP; ++s) {
-    const T dh = nd[0][s], hu = nd[1][s], hv = nd[2][s];
+  // node terms: F (x 1/R), G (x cos/R) and the two momentum sources
+  auto node_terms = [&](int s, const T dh, const T hu, const T hv, T (&f)[8]) {
     const T hh = dh + H;
     const T rh = dg_rcp(hh);
     const T u = hu * rh, vv = hv * rh;
     const T pr = T(0.5) * grav * dh * (hh + H);
     const T c = tab[ro + S_::rCos + s];
-    const T F0 = hu * invR, F1 = (hu * u + pr) * invR, F2 = hu * vv * invR;
     const T cR = c * invR;
-    const T G0 = hv * cR, G1 = hv * u * cR, G2 = (hv * vv + pr) * cR;
+    f[0] = hu * invR; f[1] = (hu * u + pr) * invR; f[2] = hu * vv * invR;
+    f[3] = hv * cR; f[4] = hv * u * cR; f[5] = (hv * vv + pr) * cR;
     const T C = tab[ro + S_::rFc + s] + u * tab[ro + S_::rSnR + s];
-    const T S1 = C * hv, S2 = -pr * tab[ro + S_::rStR + s] - C * hu;
+    f[6] = C * hv; f[7] = -pr * tab[ro + S_::rStR + s] - C * hu;
+  };
+  // add terms q0 .. q1-1 of node s to this half's outputs
+  auto contract = [&](int s, const T *f, int q0, int q1) {
 #pragma unroll
     for (int kb = 0; kb < K0; ++kb) {
       const T bm = tab[ro + S_::rBM + s * NP + bh[kb]], dm = tab[ro + S_::rDM + s * NP + bh[kb]];
-      ZD[0][kb] += F0 * bm; ZD[1][kb] += F1 * bm; ZD[2][kb] += F2 * bm;
-      ZG[0][kb] += G0 * dm; ZG[1][kb] += G1 * dm; ZG[2][kb] += G2 * dm;
-      ZS[0][kb] += S1 * bm; ZS[1][kb] += S2 * bm;
+#pragma unroll
+      for (int q = q0; q < q1; ++q) {
+        if (q < 3) ZD[q][kb] += f[q - q0] * bm;
+        else if (q < 6) ZG[q - 3][kb] += f[q - q0] * dm;
+        else ZS[q - 6][kb] += f[q - q0] * bm;
+      }
+    }
+  };
+  constexpr int XQ = S_::XQ;
+  static_assert(!SPLIT || (8 % XQ == 0 && XQ * NP * NP <= S_::oFX && S_::oGY + 6 * NP <= S_::oFX),
+                "half-layout LDS regions");
+  if constexpr (!SPLIT) {
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      T f[8];
+      node_terms(s, nd[0][s], nd[1][s], nd[2][s], f);
+      contract(s, f, 0, 8);
+    }
+  } else {
+    static_assert(NP % 2 == 0, "SPLIT halves own K0 = NP / 2 nodes each");
+    // own nodes s = h K0 + k: contracted at once; the first XQ terms go to
+    // LDS right away, the rest wait in registers for their round
+    T own[K0][8];
+#pragma unroll
+    for (int k = 0; k < K0; ++k) {
+      const int s = h * K0 + k;
+      node_terms(s, nd[0][k], nd[1][k], nd[2][k], own[k]);
+      contract(s, own[k], 0, 8);
+#pragma unroll
+      for (int q = 0; q < XQ; ++q) S[(q * NP + t) * NP + s] = own[k][q];
+    }
+#pragma unroll
+    for (int q0 = 0; q0 < 8; q0 += XQ) {
+      if (q0 > 0) {
+#pragma unroll
+        for (int k = 0; k < K0; ++k)
+#pragma unroll
+          for (int q = 0; q < XQ; ++q) S[(q * NP + t) * NP + h * K0 + k] = own[k][q0 + q];
+      }
+      wave_sync();
+#pragma unroll
+      for (int k = 0; k < K0; ++k) {     // the other half's nodes
+        const int s = (1 - h) * K0 + k;
+        T f[XQ];
+#pragma unroll
+        for (int q = 0; q < XQ; ++q) f[q] = S[(q * NP + t) * NP + s];
+        contract(s, f, q0, q0 + XQ);
+      }
+      wave_sync();
     }
   }
   const T wt = tab[S_::oW + t], cF = gt->cF, cG = gt->cG;
@@ -873,7 +965,7 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
         res[k] = acc;
       }
     }
-    if (active) store_half<T, NP>(out + base + v * N, h, res);
+    if ((store_mask >> lane) & 1ull) store_half<T, NP>(out + base + v * N, h, res);
   }
 }
 
