@@ -169,6 +169,8 @@ int make_ctx(const dg_mesh_desc *desc, const dgsw::HostTables &t, hipStream_t s,
   }
 
   hipError_t e;
+  c->glob_bytes = gb;
+  c->rows_bytes = rb;
   if ((e = hipMalloc(&c->d_glob, gb)) != hipSuccess ||
       (e = hipMalloc(&c->d_rows, rb)) != hipSuccess ||
       (e = hipMalloc(reinterpret_cast<void **>(&c->d_mass_w), t.mass_w.size() * sizeof(double))) != hipSuccess ||

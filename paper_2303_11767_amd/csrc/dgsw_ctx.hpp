@@ -15,6 +15,7 @@ struct dg_ctx {
   size_t elem_bytes = 0;
   void *d_glob = nullptr;      // GlobTab<T, np>
   void *d_rows = nullptr;      // RowTab<T, np>[n_lat]
+  size_t glob_bytes = 0, rows_bytes = 0;   // sizes of the two
   double *d_mass_w = nullptr;  // mass diagnostic weights [n_lat][np]
   double *d_partial = nullptr; // mass partial sums
   double *d_out4 = nullptr;    // mass result

@@ -70,8 +70,8 @@ hipError_t launch_stage(int dtype, int np, const StageLaunch &a, hipStream_t s);
 // layout: the elements seg .. e_end - 1 from row j on (packed across a row
 // end, or one row's segment when e_end is that row's end).
 struct alignas(16) EnsItem {
-  const void *glob;   // GlobTab<T, np>
-  const void *rows;   // RowTab<T, np>[n_lat]
+  long long glob;     // byte offset of the member's GlobTab<T, np> in the ensemble's table copy
+  long long rows;     // byte offset of its RowTab<T, np>[n_lat] there
   long long off;      // offset of the member's state in the packed buffers (values)
   double dt;
   int n_lon, n_lat, np, j;
@@ -81,6 +81,7 @@ struct alignas(16) EnsItem {
 struct EnsLaunch {
   const void *q, *q0;
   void *out;
+  const void *tabs;     // every member's tables, one device buffer (EnsItem offsets)
   const EnsItem *items;
   const int *bounds;    // parts + 1 item offsets, one contiguous range per workgroup
   int parts, combine;

@@ -15,8 +15,8 @@ constexpr int lds_max_tab(int npmax) { return npmax == 0 ? 0 : (lds_tab(npmax) >
 constexpr int lds_max_sh(int npmax) { return npmax == 0 ? 0 : (lds_sh(npmax) > lds_max_sh(npmax - 1) ? lds_sh(npmax) : lds_max_sh(npmax - 1)); }
 
 template <typename T, int NP, int CM>
-__device__ __forceinline__ void ens_case(const EnsItem &m, const T *q, const T *q0, T *out,
-                                         int combine, T c0, T ce, int lane, T *tab, T *sh) {
+__device__ __forceinline__ void ens_case(const EnsItem &m, const unsigned char *__restrict__ tabs, const T *q,
+                                         const T *q0, T *out, int combine, T c0, T ce, int lane, T *tab, T *sh) {
   StageArgs<T, NP> A;
   A.q = q + m.off;
   A.q0 = q0 ? q0 + m.off : nullptr;
@@ -24,8 +24,8 @@ __device__ __forceinline__ void ens_case(const EnsItem &m, const T *q, const T *
   A.forcing = nullptr;
   A.qa = A.qb = nullptr;
   A.ca = A.cb = T(0);
-  A.gt = static_cast<const GlobTab<T, NP> *>(m.glob);
-  A.rows = static_cast<const RowTab<T, NP> *>(m.rows);
+  A.gt = reinterpret_cast<const GlobTab<T, NP> *>(tabs + m.glob);
+  A.rows = reinterpret_cast<const RowTab<T, NP> *>(tabs + m.rows);
   A.n_lon = m.n_lon;
   A.n_lat = m.n_lat;
   A.alpha_global = m.alpha_global;
@@ -47,6 +47,7 @@ __device__ __forceinline__ void ens_case(const EnsItem &m, const T *q, const T *
 // wave-uniform switch.
 template <typename T, int NPMAX, int WPB, int CM>
 __global__ __launch_bounds__(64 * WPB) void k_ens_stage(const T *__restrict__ q, const T *q0, T *out,
+                                                        const unsigned char *__restrict__ tabs,
                                                         const EnsItem *__restrict__ items,
                                                         const int *__restrict__ bounds, int combine,
                                                         T c0, T ce) {
@@ -59,17 +60,17 @@ __global__ __launch_bounds__(64 * WPB) void k_ens_stage(const T *__restrict__ q,
   for (int it = bounds[part] + wv; it < end; it += WPB) {
     const EnsItem m = items[it];
     switch (m.np) {
-      case 1: ens_case<T, 1, CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
-      case 2: ens_case<T, 2, CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
-      case 3: ens_case<T, 3, CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
-      case 4: ens_case<T, 4, CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
-      case 5: ens_case<T, 5, CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 1: ens_case<T, 1, CM>(m, tabs, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 2: ens_case<T, 2, CM>(m, tabs, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 3: ens_case<T, 3, CM>(m, tabs, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 4: ens_case<T, 4, CM>(m, tabs, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+      case 5: ens_case<T, 5, CM>(m, tabs, q, q0, out, combine, c0, ce, lane, tab, sh); break;
       default:
         if constexpr (NPMAX > 5) {
           switch (m.np) {
-            case 6: ens_case<T, (NPMAX > 5 ? 6 : 1), CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
-            case 7: ens_case<T, (NPMAX > 6 ? 7 : 1), CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
-            case 8: ens_case<T, (NPMAX > 7 ? 8 : 1), CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+            case 6: ens_case<T, (NPMAX > 5 ? 6 : 1), CM>(m, tabs, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+            case 7: ens_case<T, (NPMAX > 6 ? 7 : 1), CM>(m, tabs, q, q0, out, combine, c0, ce, lane, tab, sh); break;
+            case 8: ens_case<T, (NPMAX > 7 ? 8 : 1), CM>(m, tabs, q, q0, out, combine, c0, ce, lane, tab, sh); break;
             default: break;
           }
         }
@@ -81,8 +82,8 @@ __global__ __launch_bounds__(64 * WPB) void k_ens_stage(const T *__restrict__ q,
 // The same for the half layout (2 NP lanes per element); items give their
 // element range.
 template <typename T, int NP>
-__device__ __forceinline__ StageArgs<T, NP> ens_args(const EnsItem &m, const T *q, const T *q0, T *out,
-                                                     int combine, T c0, T ce) {
+__device__ __forceinline__ StageArgs<T, NP> ens_args(const EnsItem &m, const unsigned char *__restrict__ tabs,
+                                                     const T *q, const T *q0, T *out, int combine, T c0, T ce) {
   StageArgs<T, NP> A;
   A.q = q + m.off;
   A.q0 = q0 ? q0 + m.off : nullptr;
@@ -90,8 +91,8 @@ __device__ __forceinline__ StageArgs<T, NP> ens_args(const EnsItem &m, const T *
   A.forcing = nullptr;
   A.qa = A.qb = nullptr;
   A.ca = A.cb = T(0);
-  A.gt = static_cast<const GlobTab<T, NP> *>(m.glob);
-  A.rows = static_cast<const RowTab<T, NP> *>(m.rows);
+  A.gt = reinterpret_cast<const GlobTab<T, NP> *>(tabs + m.glob);
+  A.rows = reinterpret_cast<const RowTab<T, NP> *>(tabs + m.rows);
   A.n_lon = m.n_lon;
   A.n_lat = m.n_lat;
   A.alpha_global = m.alpha_global;
@@ -115,12 +116,12 @@ struct EnsLds {
 };
 
 template <typename T, int NP, int LAY, int CM>
-__device__ __forceinline__ void ens_item(const EnsItem &m, const T *q, const T *q0, T *out, int combine, T c0,
-                                         T ce, int lane, T *tab, T *sh) {
+__device__ __forceinline__ void ens_item(const EnsItem &m, const unsigned char *__restrict__ tabs, const T *q,
+                                         const T *q0, T *out, int combine, T c0, T ce, int lane, T *tab, T *sh) {
   if constexpr (LAY == 0) {
-    ens_case<T, NP, CM>(m, q, q0, out, combine, c0, ce, lane, tab, sh);
+    ens_case<T, NP, CM>(m, tabs, q, q0, out, combine, c0, ce, lane, tab, sh);
   } else {
-    stage_wave_h2<T, NP, CM, true>(ens_args<T, NP>(m, q, q0, out, combine, c0, ce), m.j, m.seg, m.e_end, lane,
+    stage_wave_h2<T, NP, CM, true>(ens_args<T, NP>(m, tabs, q, q0, out, combine, c0, ce), m.j, m.seg, m.e_end, lane,
                                    tab, sh);
   }
 }
@@ -131,6 +132,7 @@ __device__ __forceinline__ void ens_item(const EnsItem &m, const T *q, const T *
 // budget and occupancy.
 template <typename T, int NP, int LAY, int WPB, int CM>
 __global__ __launch_bounds__(64 * WPB) void k_ens_stage_np(const T *__restrict__ q, const T *q0, T *out,
+                                                           const unsigned char *__restrict__ tabs,
                                                            const EnsItem *__restrict__ items,
                                                            const int *__restrict__ bounds, int combine,
                                                            T c0, T ce) {
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(64 * WPB) void k_ens_stage_np(const T *__restrict__
   const int end = bounds[part + 1];
   for (int it = bounds[part] + wv; it < end; it += WPB) {
     const EnsItem m = items[it];
-    ens_item<T, NP, LAY, CM>(m, q, q0, out, combine, c0, ce, lane, tab_all[wv], sh_all[wv]);
+    ens_item<T, NP, LAY, CM>(m, tabs, q, q0, out, combine, c0, ce, lane, tab_all[wv], sh_all[wv]);
   }
 }
 
@@ -150,6 +152,7 @@ __global__ __launch_bounds__(64 * WPB) void k_ens_stage_np(const T *__restrict__
 // (no loop: same register budget as the single-mesh kernel).
 template <typename T, int NP, int LAY, int WPB, int CM>
 __global__ __launch_bounds__(64 * WPB) void k_ens_stage_flat(const T *__restrict__ q, const T *q0, T *out,
+                                                             const unsigned char *__restrict__ tabs,
                                                              const EnsItem *__restrict__ items,
                                                              int begin, int end, int combine, T c0, T ce) {
   __shared__ T tab_all[WPB][EnsLds<T, NP, LAY>::TB];
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(64 * WPB) void k_ens_stage_flat(const T *__restrict
   const int it = begin + xcd_block(blockIdx.x, gridDim.x) * WPB + wv;
   if (it >= end) return;
   const EnsItem m = items[it];
-  ens_item<T, NP, LAY, CM>(m, q, q0, out, combine, c0, ce, lane, tab_all[wv], sh_all[wv]);
+  ens_item<T, NP, LAY, CM>(m, tabs, q, q0, out, combine, c0, ce, lane, tab_all[wv], sh_all[wv]);
 }
 
 // the combination mode is a template parameter of the ensemble kernels too:
@@ -169,11 +172,13 @@ static hipError_t launch_ens_flat_t(const EnsLaunch &a, hipStream_t s) {
   const dim3 grid((n + WPB - 1) / WPB), block(64 * WPB);
   if (a.combine)
     hipLaunchKernelGGL((k_ens_stage_flat<T, NP, LAY, WPB, 1>), grid, block, 0, s, static_cast<const T *>(a.q),
-                       static_cast<const T *>(a.q0), static_cast<T *>(a.out), a.items, a.begin, a.end, 1, T(a.c0),
+                       static_cast<const T *>(a.q0), static_cast<T *>(a.out),
+                       static_cast<const unsigned char *>(a.tabs), a.items, a.begin, a.end, 1, T(a.c0),
                        T(a.c0 + a.c1 - 1.0));
   else
     hipLaunchKernelGGL((k_ens_stage_flat<T, NP, LAY, WPB, 0>), grid, block, 0, s, static_cast<const T *>(a.q),
-                       static_cast<const T *>(a.q0), static_cast<T *>(a.out), a.items, a.begin, a.end, 0, T(a.c0),
+                       static_cast<const T *>(a.q0), static_cast<T *>(a.out),
+                       static_cast<const unsigned char *>(a.tabs), a.items, a.begin, a.end, 0, T(a.c0),
                        T(a.c0 + a.c1 - 1.0));
   return hipGetLastError();
 }
@@ -182,11 +187,13 @@ template <typename T, int NP, int LAY, int WPB>
 static hipError_t launch_ens_np_t(const EnsLaunch &a, hipStream_t s) {
   if (a.combine)
     hipLaunchKernelGGL((k_ens_stage_np<T, NP, LAY, WPB, 1>), dim3(a.parts), dim3(64 * WPB), 0, s,
-                       static_cast<const T *>(a.q), static_cast<const T *>(a.q0), static_cast<T *>(a.out), a.items,
+                       static_cast<const T *>(a.q), static_cast<const T *>(a.q0), static_cast<T *>(a.out),
+                       static_cast<const unsigned char *>(a.tabs), a.items,
                        a.bounds, 1, T(a.c0), T(a.c0 + a.c1 - 1.0));
   else
     hipLaunchKernelGGL((k_ens_stage_np<T, NP, LAY, WPB, 0>), dim3(a.parts), dim3(64 * WPB), 0, s,
-                       static_cast<const T *>(a.q), static_cast<const T *>(a.q0), static_cast<T *>(a.out), a.items,
+                       static_cast<const T *>(a.q), static_cast<const T *>(a.q0), static_cast<T *>(a.out),
+                       static_cast<const unsigned char *>(a.tabs), a.items,
                        a.bounds, 0, T(a.c0), T(a.c0 + a.c1 - 1.0));
   return hipGetLastError();
 }
@@ -227,11 +234,13 @@ template <typename T, int NPMAX, int WPB>
 static hipError_t launch_ens_t(const EnsLaunch &a, hipStream_t s) {
   if (a.combine)
     hipLaunchKernelGGL((k_ens_stage<T, NPMAX, WPB, 1>), dim3(a.parts), dim3(64 * WPB), 0, s,
-                       static_cast<const T *>(a.q), static_cast<const T *>(a.q0), static_cast<T *>(a.out), a.items,
+                       static_cast<const T *>(a.q), static_cast<const T *>(a.q0), static_cast<T *>(a.out),
+                       static_cast<const unsigned char *>(a.tabs), a.items,
                        a.bounds, 1, T(a.c0), T(a.c0 + a.c1 - 1.0));
   else
     hipLaunchKernelGGL((k_ens_stage<T, NPMAX, WPB, 0>), dim3(a.parts), dim3(64 * WPB), 0, s,
-                       static_cast<const T *>(a.q), static_cast<const T *>(a.q0), static_cast<T *>(a.out), a.items,
+                       static_cast<const T *>(a.q), static_cast<const T *>(a.q0), static_cast<T *>(a.out),
+                       static_cast<const unsigned char *>(a.tabs), a.items,
                        a.bounds, 0, T(a.c0), T(a.c0 + a.c1 - 1.0));
   return hipGetLastError();
 }

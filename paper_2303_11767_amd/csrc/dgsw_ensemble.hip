@@ -29,6 +29,11 @@ struct dg_ens {
   std::vector<double> dt;                // per member
   dgsw::EnsItem *d_items = nullptr;
   int *d_bounds = nullptr;
+  // every member's GlobTab and RowTab array copied into one buffer, so the
+  // kernels reach them from a kernel argument (scalar loads of the uniform
+  // table reads) through the byte offsets in the work items
+  unsigned char *d_tabs = nullptr;
+  std::vector<long long> tab_glob, tab_rows;   // per member
   int bounds_cap = 0;
   int wpb = 4, parts = 0, fused = 0, flat = 1;
   std::vector<int> layout;               // per member: DG_KERNEL_LINE or DG_KERNEL_HALF
@@ -56,6 +61,7 @@ void ens_release(dg_ens *e) {
   for (dg_ctx *c : e->members) dg_free(c);
   if (e->d_items) (void)hipFree(e->d_items);
   if (e->d_bounds) (void)hipFree(e->d_bounds);
+  if (e->d_tabs) (void)hipFree(e->d_tabs);
   delete e;
 }
 
@@ -71,8 +77,8 @@ int build_items(dg_ens *e) {
     const int lay = e->layout[m];
     dgsw::EnsItem it;
     std::memset(&it, 0, sizeof(it));
-    it.glob = c->d_glob;
-    it.rows = c->d_rows;
+    it.glob = e->tab_glob[m];
+    it.rows = e->tab_rows[m];
     it.off = e->off[m];
     it.dt = e->dt.empty() ? 0.0 : e->dt[m];
     it.n_lon = c->d.n_lon;
@@ -211,6 +217,7 @@ int ens_stage(dg_ens *e, const void *q, const void *q0, void *out, int combine, 
   a.q = q;
   a.q0 = q0;
   a.out = out;
+  a.tabs = e->d_tabs;
   a.items = e->d_items;
   a.combine = combine;
   a.c0 = c0;
@@ -288,6 +295,34 @@ int dg_ens_init(const dg_mesh_desc *members, int32_t n_members, void *hip_stream
   if (e->off[n_members] >= (int64_t(1) << 31)) {
     ens_release(e);
     return fail(DG_EINVAL, "packed ensemble state exceeds 2^31 values");
+  }
+  {
+    // the members' tables, each at a 256-byte aligned offset of one buffer
+    auto up = [](size_t b) { return (long long)((b + 255) / 256 * 256); };
+    long long total = 0;
+    for (const dg_ctx *c : e->members) {
+      e->tab_glob.push_back(total);
+      total += up(c->glob_bytes);
+      e->tab_rows.push_back(total);
+      total += up(c->rows_bytes);
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipError_t err = hipMalloc(reinterpret_cast<void **>(&e->d_tabs), (size_t)total);
+    if (err != hipSuccess) {
+      ens_release(e);
+      return fail(DG_ENOMEM, "hipMalloc of the ensemble's table copy");
+    }
+    for (int m = 0; m < n_members && err == hipSuccess; ++m) {
+      const dg_ctx *c = e->members[m];
+      err = hipMemcpyAsync(e->d_tabs + e->tab_glob[m], c->d_glob, c->glob_bytes, hipMemcpyDeviceToDevice, s);
+      if (err == hipSuccess)
+        err = hipMemcpyAsync(e->d_tabs + e->tab_rows[m], c->d_rows, c->rows_bytes, hipMemcpyDeviceToDevice, s);
+    }
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) {
+      ens_release(e);
+      return hip_fail(err, "copy of the members' tables");
+    }
   }
   {
     const int rc = build_items(e);

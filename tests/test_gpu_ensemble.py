@@ -106,19 +106,35 @@ ORDERS = sorted({m["order"] for m in MEMBERS})
 
 def test_schedule_does_not_change_results(dg):
     """With every member in the line layout (the fused launch runs that layout
-    only): per-order and fused schedules of any shape give bitwise the same
-    stage."""
+    only): per-order and fused schedules of any shape give the same stage to
+    rounding (each schedule runs its own compiled kernel, whose multiply-add
+    contraction may differ), and every schedule is bitwise reproducible."""
     say("schedules")
     ens, q, dts = build(dg, "f32")
     for o in ORDERS:
         ens.set_kernel(o, "line")
     ref = ens.empty_state()
     ens.rk_stage(q, None, ref, 0.0, 1.0)
+
+    def rel_err(out):
+        # per member and variable, against that variable's largest value
+        worst = 0.0
+        for m, o, r in zip(ens.members, ens.views(out), ens.views(ref)):
+            o3, r3 = o.double().view(m.E, 3, -1), r.double().view(m.E, 3, -1)
+            for v in range(3):
+                d = (o3[:, v] - r3[:, v]).abs().max().item()
+                worst = max(worst, d / max(r3[:, v].abs().max().item(), 1e-300))
+        return worst
+
     for w, g, f in [(1, 1, 0), (1, 7, 1), (2, 64, 0), (4, 3, 1), (4, 1000, 0), (2, 100000, 1), (4, 0, 0), (2, 0, 1)]:
         ens.set_schedule(w, g, f)
-        out = ens.empty_state()
+        out, again = ens.empty_state(), ens.empty_state()
         ens.rk_stage(q, None, out, 0.0, 1.0)
-        assert torch.equal(out, ref), (w, g)
+        ens.rk_stage(q, None, again, 0.0, 1.0)
+        err = rel_err(out)
+        say("  schedule", w, g, f, "bitwise" if torch.equal(out, ref) else f"rel {err:.2e}")
+        assert torch.equal(out, again), (w, g, f)
+        assert err <= 1e-6, (w, g, f, err)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
