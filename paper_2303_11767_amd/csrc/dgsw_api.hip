@@ -93,18 +93,20 @@ int make_ctx(const dg_mesh_desc *desc, const dgsw::HostTables &t, hipStream_t s,
   dg_ctx *c = new dg_ctx();
   c->d = *desc;
   c->periodic_y = t.periodic_y ? 1 : 0;
-  // kernel layout, chosen from MI355X stage timings of both layouts: the
-  // half-line layout where the line layout leaves the GPU latency-bound (at
-  // most 2048 wavefronts, about two per SIMD), for FP64 at r >= 5, where the
-  // line layout's registers allow only one wavefront per SIMD, for FP64 at
-  // r = 3, where it holds four wavefronts per SIMD against the line layout's
-  // two, and for FP64 at r = 1 (360 x 180: 10.8 against 13.1 us per stage);
-  // the line layout otherwise (dg_autotune measures instead)
+  // kernel layout, chosen from MI355X stage timings of both layouts over
+  // r = 1..5, 90x45 .. 720x360 and both precisions: the half-line layout at
+  // r = 1 (its 4 lanes per element against the line layout's 2), for FP64 at
+  // r >= 5, where the line layout's registers allow only one wavefront per
+  // SIMD, for FP64 at r = 3, where it holds four wavefronts per SIMD against
+  // the line layout's two, and where the line layout leaves the GPU
+  // latency-bound (at most 2048 wavefronts, about two per SIMD; at r >= 4,
+  // where the work the two halves duplicate costs more, at most 512); the
+  // line layout otherwise (dg_autotune measures instead)
   {
     const int waves_line = dgsw::waves_per_row(desc->order + 1, desc->n_lon) * desc->n_lat;
-    const bool half =
-        (desc->dtype == DG_F64 && (desc->order >= 5 || desc->order == 3 || desc->order == 1)) ||
-        waves_line <= 2048;
+    const bool half = desc->order == 1 ||
+                      (desc->dtype == DG_F64 && (desc->order >= 5 || desc->order == 3)) ||
+                      waves_line <= (desc->order >= 4 ? 512 : 2048);
     c->kernel = half ? DG_KERNEL_HALF : DG_KERNEL_LINE;
   }
   c->np = desc->order + 1;
