@@ -202,6 +202,22 @@ def run(args):
     torch.cuda.synchronize()
     eager_s = ev0.elapsed_time(ev1) * 1e-3
 
+    # dg_rhs alone (dq/dt = M^-1 h(q), no stage combination): blocks of 100
+    # calls between events, the median of the repeats; 2 state transfers each
+    rhs_out = torch.empty_like(q)
+    mesh.rhs(q, rhs_out, stream=stream)
+    rhs_t = []
+    for _ in range(max(1, args.repeats)):
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(100):
+            mesh.rhs(q, rhs_out, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        rhs_t.append(ev0.elapsed_time(ev1) * 1e-3 / 100)
+    rhs_s = sorted(rhs_t)[len(rhs_t) // 2]
+    del rhs_out
+
     # the stage kernel alone: events around every launch of full 3-stage
     # cycles on the launch stream (for reference)
     w0, w1 = work[: q.numel()].view_as(q), work[q.numel():].view_as(q)
@@ -257,6 +273,9 @@ def run(args):
         "timed_with": f"HIP graph of {chunk} steps replayed {args.steps // chunk} times; "
                       f"median of {len(reps)} repeats of the {args.steps}-step region",
         "value_eager_launches": dofs * 3 * args.steps / eager_s,
+        "rhs_alone": {"us_per_call": rhs_s * 1e6, "dof_per_s": dofs / rhs_s,
+                      "alg_GBs": 2.0 * state_bytes / rhs_s / 1e9,
+                      "timed_with": "100 back-to-back dg_rhs calls between events, median of the repeats"},
     }
     return out
 
@@ -422,6 +441,111 @@ def learned_section(model_path, fields, seeds=LEARNED_SEEDS, t_eval=LEARNED_HORI
                           fields=fields)
     rep["model"] = os.path.relpath(model_path, ROOT)
     return rep
+
+
+def mesh_section(n_lon, n_lat, order, dtype, lmax, seed, steps, repeats=5, graph=False):
+    """SSP-RK3 throughput of one plain mesh: `steps` steps between events
+    (replayed from a HIP graph of those steps when `graph`), median of
+    `repeats`; the stage kernel's algorithmic bandwidth (8/3 of the state per
+    launch) at the mean stage duration."""
+    import numpy as np
+    import torch
+
+    import paper_2303_11767_amd as dg
+    from dg_inputs import band_limited_state
+    q_h, info = band_limited_state(n_lon, n_lat, order, lmax, seed)
+    mesh = dg.Mesh(n_lon, n_lat, order, dtype=dtype, h_ref=1.0e4 if dtype == "f32" else 0.0)
+    q = torch.from_numpy(q_h).to(device="cuda", dtype=mesh.dtype).contiguous()
+    work = mesh.empty_work()
+    dt = dg.cfl_time_step(mesh, info.cmax, CFL)
+    stream = torch.cuda.current_stream()
+    mesh.rk_step(q, work, dt, nsteps=10)
+    g = mesh.graph(q, work, dt, nsteps=steps) if graph else None
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        e0.record(stream)
+        if g is not None:
+            g.launch(stream)
+        else:
+            mesh.rk_step(q, work, dt, nsteps=steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(e0.elapsed_time(e1) * 1e-3 / steps)
+    if g is not None:
+        g.close()
+    if not all(np.isfinite(mesh.mass(q))):
+        raise RuntimeError(f"{n_lon}x{n_lat} r={order} run became non-finite")
+    step_s = sorted(reps)[len(reps) // 2]
+    dofs = 3 * mesh.E * mesh.N
+    alg = 8.0 * dofs * q.element_size() / 3.0
+    out = {"workload": f"plain DG SWE, r={order}, {n_lon}x{n_lat} lat-lon elements, {dtype.upper()}, SSP-RK3, "
+                       f"CFL 0.1, band-limited l<={lmax} seed {seed}",
+           "dofs": dofs, "steps": steps, "kernel": mesh.kernel, "ms_per_step": step_s * 1e3,
+           "repeats_ms_per_step": [r * 1e3 for r in reps], "dof_updates_per_s": dofs * 3 / step_s,
+           "timed_with": ("HIP graph of the steps" if graph else "eager launches") + f", median of {repeats}",
+           "roofline": {"bound": "hbm", "achieved": alg / (step_s / 3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": alg / (step_s / 3) / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_launch": alg,
+                        "launch_us": step_s / 3 * 1e6}}
+    del q, work
+    torch.cuda.empty_cache()
+    return out
+
+
+def contraction_ab(n_elem=64800, reps=50):
+    """The r = 5 FP32 volume contraction in its sum-factorised VALU form and
+    its dense MFMA form (see probe_contraction), as a dict."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2303_11767_amd", "libdgsw_probe.so"))
+    lib.dgp_contraction_time.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_double)]
+    lib.dgp_contraction_check.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    out = {"probe": "volume contraction r=5 FP32 over the 360x180 elements", "n_elem": n_elem, "reps": reps}
+    for name, variant in (("valu_sum_factorised", 0), ("mfma_dense", 1)):
+        ms = ctypes.c_double()
+        rc = lib.dgp_contraction_time(variant, n_elem, reps, ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"contraction probe {name}: error {rc}")
+        out[name] = {"us_per_launch": ms.value * 1e3, "ns_per_element": ms.value * 1e6 / n_elem}
+    rel = ctypes.c_double()
+    if lib.dgp_contraction_check(4096, ctypes.byref(rel)) != 0:
+        raise RuntimeError("contraction probe check failed")
+    out["max_rel_difference"] = rel.value
+    out["mfma_over_valu_time"] = out["mfma_dense"]["us_per_launch"] / out["valu_sum_factorised"]["us_per_launch"]
+    return out
+
+
+# the configurations the oracle is timed on: name, n_lon, n_lat, order, l_max, seed
+ORACLE_CONFIGS = (("C1", 32, 16, 1, 6, 1), ("C2", 180, 90, 3, 16, 2), ("C3", 360, 180, 5, 32, 3),
+                  ("C5", 360, 180, 1, 32, 200))
+
+
+def oracle_timings():
+    """The FP64 oracle, as it stands, on one host thread: one right-hand side
+    and one SSP-RK3 step per configuration (seconds and DOF-updates/s), each
+    timed after one untimed call of the same kind."""
+    from threadpoolctl import threadpool_limits
+    from dg_inputs import band_limited_state
+    from oracle import SphereDG
+    out = {}
+    with threadpool_limits(limits=1):
+        for name, nl, nt, r, lmax, seed in ORACLE_CONFIGS:
+            q, info = band_limited_state(nl, nt, r, lmax, seed)
+            m = SphereDG(nl, nt, r)
+            dofs = 3 * m.E * m.N
+            m.rhs(q)
+            t0 = time.perf_counter()
+            m.rhs(q)
+            t_rhs = time.perf_counter() - t0
+            dt = m.cfl_time_step(info.cmax, CFL)
+            m.ssp_rk3_step(q, dt)
+            t0 = time.perf_counter()
+            m.ssp_rk3_step(q, dt)
+            t_step = time.perf_counter() - t0
+            out[name] = {"mesh": f"{nl}x{nt} r={r}", "dofs": dofs, "rhs_s": t_rhs, "step_s": t_step,
+                         "rhs_dof_per_s": dofs / t_rhs, "step_dof_updates_per_s": 3 * dofs / t_step}
+    return out
 
 
 def planar_section(dtype="f64"):
@@ -654,30 +778,12 @@ def profile_probe_ensemble(args):
                       "state_bytes": ens.size * 4, "steps": args.steps, "copy_bytes": nbytes}), flush=True)
 
 
-def probe_contraction(n_elem=64800, reps=50):
-    """The volume-integral contraction alone at r = 5 in FP32 on the elements
-    of the 360 x 180 mesh, in the sum-factorised VALU form the stage kernels
-    use and in the dense MFMA form (libdgsw_probe.so; nodal values synthesised
-    in registers, so no memory traffic): time per launch of each, and the
-    largest difference between their results."""
-    import ctypes
-    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2303_11767_amd", "libdgsw_probe.so"))
-    lib.dgp_contraction_time.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                         ctypes.POINTER(ctypes.c_double)]
-    lib.dgp_contraction_check.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
-    out = {"probe": "contraction r=5 FP32", "n_elem": n_elem, "reps": reps}
-    for name, variant in (("valu_sum_factorised", 0), ("mfma_dense", 1)):
-        ms = ctypes.c_double()
-        rc = lib.dgp_contraction_time(variant, n_elem, reps, ctypes.byref(ms))
-        if rc != 0:
-            raise RuntimeError(f"contraction probe {name}: error {rc}")
-        out[name] = {"us_per_launch": ms.value * 1e3, "ns_per_element": ms.value * 1e6 / n_elem}
-    rel = ctypes.c_double()
-    if lib.dgp_contraction_check(4096, ctypes.byref(rel)) != 0:
-        raise RuntimeError("contraction probe check failed")
-    out["max_rel_difference"] = rel.value
-    out["mfma_over_valu_time"] = out["mfma_dense"]["us_per_launch"] / out["valu_sum_factorised"]["us_per_launch"]
-    print(json.dumps(out), flush=True)
+def probe_contraction():
+    """The r = 5 FP32 volume contraction alone, in the sum-factorised VALU form
+    the stage kernels use and the dense MFMA form (libdgsw_probe.so; nodal
+    values synthesised in registers, so no memory traffic): time per launch
+    of each and the largest difference between their results."""
+    print(json.dumps(contraction_ab()), flush=True)
 
 
 def main():
@@ -731,7 +837,7 @@ def main():
         import multiprocessing as mp
         from concurrent.futures import ProcessPoolExecutor
         pool = ProcessPoolExecutor(max_workers=6, mp_context=mp.get_context("fork"))
-        futs = {"big": pool.submit(big_fields)}
+        futs = {"big": pool.submit(big_fields), "oracle": pool.submit(oracle_timings)}
         if os.path.exists(LEARNED_MODEL):
             futs.update({s: pool.submit(learned_fields, s) for s in LEARNED_SEEDS})
     out = run(args)
@@ -749,10 +855,19 @@ def main():
         out["advection"] = advection_section()
         out["scaling_studies"] = scaling_section()
         out["large_mesh"] = big_section(futs.pop("big").result(), probe)
+        out["small_mesh_c1"] = mesh_section(32, 16, 1, "f64", 6, 1, steps=100, graph=True)
+        out["order5_c3"] = mesh_section(360, 180, 5, "f32", 32, 3, steps=50)
+        out["order5_c3"]["contraction_valu_vs_mfma"] = contraction_ab()
         if os.path.exists(LEARNED_MODEL):
             out["learned"] = learned_section(LEARNED_MODEL, lambda seed: futs[seed].result())
+    # the per-configuration oracle timings ran in a worker beside the GPU
+    # sections; they end before the all-core baseline starts
+    oracle_cfg = futs.pop("oracle").result() if futs is not None else None
+    if pool is not None:
         pool.shutdown()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
+    if out["cpu_baseline"] is not None and oracle_cfg is not None:
+        out["cpu_baseline"]["oracle_per_config"] = oracle_cfg
     print(json.dumps(out), flush=True)
 
 
