@@ -516,6 +516,27 @@ def contraction_ab(n_elem=64800, reps=50):
     return out
 
 
+def latency_floor(n_lon=N_LON, n_lat=N_LAT, reps=300):
+    """The floor under one stage of the benchmark mesh (libdgsw_probe.so),
+    per launch with the FP64 r = 3 half layout's grid, back to back on one
+    stream and as the nodes of one graph: a kernel that does nothing, one
+    that moves the stage's own bytes (q and q^n in, the new state out) and
+    one that adds the neighbour reads of the stage."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2303_11767_amd", "libdgsw_probe.so"))
+    lib.dgp_floor_time.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_double)]
+    out = {"mesh": f"{n_lon}x{n_lat} r=3 FP64", "launches": reps, "unit": "us per launch"}
+    for mode, graph in (("eager", 0), ("graph", 1)):
+        out[mode] = {}
+        for name, variant in (("empty", 0), ("own_bytes", 1), ("own_and_neighbour_bytes", 2)):
+            us = ctypes.c_double()
+            rc = lib.dgp_floor_time(variant, n_lon, n_lat, graph, reps, ctypes.byref(us))
+            if rc != 0:
+                raise RuntimeError(f"floor probe {mode} {name}: error {rc}")
+            out[mode][name] = us.value
+    return out
+
+
 # the configurations the oracle is timed on: name, n_lon, n_lat, order, l_max, seed
 ORACLE_CONFIGS = (("C1", 32, 16, 1, 6, 1), ("C2", 180, 90, 3, 16, 2), ("C3", 360, 180, 5, 32, 3),
                   ("C5", 360, 180, 1, 32, 200))
@@ -850,6 +871,7 @@ def main():
         probe = hbm_probe()
         out["hbm_copy_probe"] = probe
         out["roofline"]["frac_of_copy_probe"] = out["roofline"]["achieved"] / probe["GBs"]
+        out["latency_floor"] = latency_floor()
         out["ensemble"] = ensemble_section()
         out["planar"] = planar_section()
         out["advection"] = advection_section()

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdgsw.so")
-PROBE_SRC = "probe_contraction.hip"
+PROBE_SRC = ["probe_contraction.hip", "probe_floor.hip"]
 PROBE_LIB = os.path.join(PKG, "libdgsw_probe.so")
 SOURCES = ["dgsw_tables.cpp", "dgsw_kernels.hip", "dgsw_ens_kernels.hip", "dgsw_api.hip",
            "dgsw_ensemble.hip", "dgsw_mlp.hip", "dgsw_learned.hip", "dgsw_advection.hip"]
@@ -55,9 +55,10 @@ def build(verbose=False, jobs=None):
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "--offload-arch=" + ARCH, "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)
-    # the contraction-throughput probe: a measurement, not part of the solver
+    # the measurement probes (contraction forms, launch and memory floor): not
+    # part of the solver
     ptmp = PROBE_LIB + ".tmp"
-    _run([HIPCC] + COMMON + DEVICE + ["-shared", "-o", ptmp, os.path.join(CSRC, PROBE_SRC)], verbose)
+    _run([HIPCC] + COMMON + DEVICE + ["-shared", "-o", ptmp] + [os.path.join(CSRC, f) for f in PROBE_SRC], verbose)
     os.replace(ptmp, PROBE_LIB)
     return LIB
 

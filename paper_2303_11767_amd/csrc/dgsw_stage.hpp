@@ -165,7 +165,7 @@ __device__ __forceinline__ void rusanov_lambda(const T qm[3], const T qp[3], T H
   T a = alpha_fixed;
   if (!fixed) {
     const T sm = fabs(m.u) + m.c, sp = fabs(p.u) + p.c;
-    a = sm > sp ? sm : sp;
+    a = fmax(sm, sp);
   }
   a *= sgn;
   out[0] = T(0.5) * (qm[1] + qp[1]) - T(0.5) * a * (qp[0] - qm[0]);
@@ -182,7 +182,7 @@ __device__ __forceinline__ void rusanov_theta(const T qm[3], const T qp[3], T H,
   T a = alpha_fixed;
   if (!fixed) {
     const T sm = fabs(m.v) + m.c, sp = fabs(p.v) + p.c;
-    a = sm > sp ? sm : sp;
+    a = fmax(sm, sp);
   }
   a *= sgn;
   out[0] = T(0.5) * (qm[2] + qp[2]) - T(0.5) * a * (qp[0] - qm[0]);
@@ -589,6 +589,24 @@ __device__ __forceinline__ void store_half(T *row, int h, const T (&r)[ShapeH2<T
   }
 }
 
+// An integer the compiler must treat as unknown: values derived from it are
+// recomputed rather than reused from earlier in the kernel (no instruction).
+__device__ __forceinline__ int opaque_int(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// The state offset of lane `lane`'s element and modal row in the half layout
+// (tail and spare lanes on the last valid element).
+template <int NP, int GPW>
+__device__ __forceinline__ size_t h2_row_offset(int lane, int e0, int e_end) {
+  int g = lane / (2 * NP), r = lane - g * 2 * NP;
+  if (g >= GPW) { g = GPW; r = lane - GPW * 2 * NP; }
+  const int t = r >= NP ? r - NP : r;
+  const int e = e0 + g < e_end ? e0 + g : e_end - 1;
+  return (size_t)e * 3 * NP * NP + (size_t)t * NP;
+}
+
 // The wavefront takes the GPW consecutive elements e0 .. e0 + GPW - 1 below
 // e_end (lanes past it idle), starting in row j0.  PK = false: a row-aligned
 // segment (e_end = the end of row j0); PK = true: elements packed across
@@ -631,9 +649,9 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
   const int i = e - j * n_lon;
   const int ro = S_::G1 + rsel * S_::RP;                 // this lane's row tables in LDS
   T *S = sh + g * SH;
-  const bool periodic = A.periodic_y != 0;
-  const bool hasN = periodic || j < n_lat - 1, hasS = periodic || j > 0;
-  const bool hasY = h ? hasS : hasN;                 // this half's latitude edge
+  // neighbours; across a pole (sphere) the latitude neighbour is the element
+  // of the row at the other end of the grid (the plane's periodic neighbour),
+  // read but weighted by the pole edge's zero cosine
   const int eE = (i + 1 == n_lon) ? e + 1 - n_lon : e + 1;
   const int eW = (i == 0) ? e - 1 + n_lon : e - 1;
   const int eN = j < n_lat - 1 ? e + n_lon : i;
@@ -643,6 +661,13 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
   const bool fixed = A.alpha_global != 0;
   const T alpha = gt->alpha;
 
+  {
+    const T *g0 = &gt->B[0][0], *ra = &A.rows[j0].cosn[0];
+    const T *rb = &A.rows[j0 + 1 < n_lat ? j0 + 1 : j0].cosn[0];
+    constexpr int TBU = PK ? S_::TB : S_::G1 + S_::RP;     // the second row only when packed
+    for (int k = lane; k < TBU; k += 64)
+      tab[k] = k < S_::G1 ? g0[k] : (k < S_::G1 + S_::RP ? ra[k - S_::G1] : rb[k - S_::G1 - S_::RP]);
+  }
   // ---- global loads: own row b = t, this half's longitude neighbour row and
   // latitude neighbour column
   const size_t row_off = (size_t)t * NP;
@@ -653,24 +678,14 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
     load_row<T, NP>(q + base + v * N, qr[v]);
     load_row<T, NP>(q + (size_t)eX * 3 * N + row_off + v * N, xX[v]);
   }
-  if (hasY) {
+  {
+    // eY is a valid element at a pole edge too (the row across the grid),
+    // whose trace the zero pole flux then discards: no branch, no zero fill
     const T *c = q + (size_t)eY * 3 * N + t;
 #pragma unroll
     for (int v = 0; v < 3; ++v)
 #pragma unroll
       for (int k = 0; k < NP; ++k) xY[v][k] = c[v * N + k * NP];
-  } else {
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-      for (int k = 0; k < NP; ++k) xY[v][k] = T(0);
-  }
-  {
-    const T *g0 = &gt->B[0][0], *ra = &A.rows[j0].cosn[0];
-    const T *rb = &A.rows[j0 + 1 < n_lat ? j0 + 1 : j0].cosn[0];
-    constexpr int TBU = PK ? S_::TB : S_::G1 + S_::RP;     // the second row only when packed
-    for (int k = lane; k < TBU; k += 64)
-      tab[k] = k < S_::G1 ? g0[k] : (k < S_::G1 + S_::RP ? ra[k - S_::G1] : rb[k - S_::G1 - S_::RP]);
   }
   // per-lane coefficients: rows h K0 + k of B (clamped), this half's own edge
   // (h = 0: +1, h = 1: -1) and the facing edge of its neighbours; from the
@@ -773,7 +788,7 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
       nx += S[NB + (h * 3 + v) * NP + b] * bt[b];
       ny += S[NB + ((2 + h) * 3 + v) * NP + b] * bt[b];
     }
-    trX[v] = ax; trY[v] = ay; nbX[v] = nx; nbY[v] = hasY ? ny : ay;
+    trX[v] = ax; trY[v] = ay; nbX[v] = nx; nbY[v] = ny;
   }
   wave_sync();
 
@@ -786,11 +801,12 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
     rusanov_lambda<T>(trX, nbX, H, grav, fixed, alpha, FhX, sgn);
     rusanov_theta<T>(trY, nbY, H, grav, fixed, alpha, GhY, sgn);
   }
-  const T fY = tab[ro + (h ? S_::rBot : S_::rTop)] * invR;     // 0 at a pole edge
+  // the edge cosine is exactly 0 at a pole edge: zero flux through the pole
+  const T fY = tab[ro + (h ? S_::rBot : S_::rTop)] * invR;
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
     FhX[v] *= invR;
-    GhY[v] = hasY ? GhY[v] * fY : T(0);
+    GhY[v] *= fY;
     S[S_::oFX + (v * 2 + h) * NP + t] = FhX[v];   // read back in the last xi pass
     S[S_::oGY + (v * 2 + h) * NP + t] = GhY[v];   // the other half's latitude edge
   }
@@ -904,15 +920,18 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
   wave_sync();
 
   // ---- epilogue operands for this half's modes a = h K0 + k of row b = t
+  // (their offset recomputed from the lane index instead of held in registers
+  // through the stage)
+  const size_t ebase = h2_row_offset<NP, GPW>(opaque_int(lane), e0, e_end);
   const bool use_q0 = combine == 2 || (combine == 1 && c0 != T(0));
   T qh[3][K0], q0h[3][K0], fh[3][K0];
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
 #pragma unroll
     for (int k = 0; k < K0; ++k) { qh[v][k] = T(0); q0h[v][k] = T(0); fh[v][k] = T(0); }
-    if (combine) load_half<T, NP>(q + base + v * N, h, qh[v]);
-    if (use_q0) load_half<T, NP>(q0 + base + v * N, h, q0h[v]);
-    if (forcing) load_half<T, NP>(forcing + base + v * N, h, fh[v]);
+    if (combine) load_half<T, NP>(q + ebase + v * N, h, qh[v]);
+    if (use_q0) load_half<T, NP>(q0 + ebase + v * N, h, q0h[v]);
+    if (forcing) load_half<T, NP>(forcing + ebase + v * N, h, fh[v]);
   }
 
   // ---- xi pass back to modes: lane t = latitude degree b, this half's a
@@ -945,8 +964,8 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
     T xa[K0], xb[K0];
 #pragma unroll
     for (int k = 0; k < K0; ++k) xa[k] = xb[k] = T(0);
-    if (combine == 2 && A.qa) load_half<T, NP>(A.qa + base + v * N, h, xa);
-    if (combine == 2 && A.qb) load_half<T, NP>(A.qb + base + v * N, h, xb);
+    if (combine == 2 && A.qa) load_half<T, NP>(A.qa + ebase + v * N, h, xa);
+    if (combine == 2 && A.qb) load_half<T, NP>(A.qb + ebase + v * N, h, xb);
     T res[K0];
 #pragma unroll
     for (int k = 0; k < K0; ++k) {
@@ -965,7 +984,7 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
         res[k] = acc;
       }
     }
-    if ((store_mask >> lane) & 1ull) store_half<T, NP>(out + base + v * N, h, res);
+    if ((store_mask >> lane) & 1ull) store_half<T, NP>(out + ebase + v * N, h, res);
   }
 }
 

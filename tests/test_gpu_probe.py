@@ -1,6 +1,8 @@
-"""The contraction probe (r = 5 FP32 volume contraction in the VALU
-sum-factorised and the MFMA dense form): both forms compute the same numbers,
-and both time positively."""
+"""The measurement probes: the contraction probe (r = 5 FP32 volume
+contraction in the VALU sum-factorised and the MFMA dense form: both forms
+compute the same numbers, and both time positively) and the launch and memory
+floor probe (every variant times positively, eagerly and as graph nodes, and
+bad arguments are refused)."""
 import ctypes
 import os
 import sys
@@ -21,6 +23,7 @@ def lib():
     lib = ctypes.CDLL(LIB)
     lib.dgp_contraction_time.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     lib.dgp_contraction_check.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.dgp_floor_time.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_double)]
     return lib
 
 
@@ -38,3 +41,20 @@ def test_forms_time(lib):
         ms = ctypes.c_double()
         assert lib.dgp_contraction_time(variant, 6480, 3, ctypes.byref(ms)) == 0
         assert ms.value > 0.0
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_floor_probe_times(lib, variant, graph):
+    us = ctypes.c_double(-1.0)
+    print("[case] floor", variant, graph, flush=True)
+    assert lib.dgp_floor_time(variant, 13, 7, graph, 10, ctypes.byref(us)) == 0
+    assert 0.0 < us.value < 1e5
+
+
+def test_floor_probe_refuses_bad_arguments(lib):
+    us = ctypes.c_double()
+    assert lib.dgp_floor_time(3, 13, 7, 0, 10, ctypes.byref(us)) == -1
+    assert lib.dgp_floor_time(0, 0, 7, 0, 10, ctypes.byref(us)) == -1
+    assert lib.dgp_floor_time(0, 13, 7, 2, 10, ctypes.byref(us)) == -1
+    assert lib.dgp_floor_time(0, 13, 7, 0, 0, ctypes.byref(us)) == -1
