@@ -6,7 +6,7 @@ namespace dgsw {
 
 // ------------------------------------------------------------------ ensemble
 // LDS of one wavefront for any order up to NPMAX
-constexpr int lds_tab(int k) { return 2 * k * k + k; }
+constexpr int lds_tab(int k) { return (2 * k * k + k + 63) / 64 * 64; }   // Shape<T, k>::TB
 constexpr int lds_sh(int k) {
   return (64 / k + 1) * ((3 * (k + 2) * k + 12 * k) > (6 * k * k + 6 * k) ? (3 * (k + 2) * k + 12 * k)
                                                                            : (6 * k * k + 6 * k));
@@ -17,6 +17,8 @@ constexpr int lds_max_sh(int npmax) { return npmax == 0 ? 0 : (lds_sh(npmax) > l
 template <typename T, int NP, int CM>
 __device__ __forceinline__ void ens_case(const EnsItem &m, const unsigned char *__restrict__ tabs, const T *q,
                                          const T *q0, T *out, int combine, T c0, T ce, int lane, T *tab, T *sh) {
+  static_assert(Shape<T, NP>::TB <= lds_tab(NP) && (Shape<T, NP>::GPW + 1) * Shape<T, NP>::SH <= lds_sh(NP),
+                "the fused kernel's LDS slices hold this order's");
   StageArgs<T, NP> A;
   A.q = q + m.off;
   A.q0 = q0 ? q0 + m.off : nullptr;

@@ -66,8 +66,10 @@ struct Shape {
   static constexpr int NB = 3 * (NP + 2) * NP;
   static constexpr int SH = cmax(NB + 12 * NP, 6 * NP * NP + 6 * NP);
   // tables read with a lane-dependent index, copied to LDS per wavefront:
-  // P~(xi_p) [p][a], weights, and the row's BM [s][b]
-  static constexpr int TB = NP * NP + NP + NP * NP;
+  // P~(xi_p) [p][a], weights, and the row's BM [s][b] (TBU values), the
+  // region rounded up to whole 64-lane rounds of the copy
+  static constexpr int TBU = NP * NP + NP + NP * NP;
+  static constexpr int TB = (TBU + 63) / 64 * 64;
   // byte alignment of one modal row (NP values) given a 16-byte aligned base
   static constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
   static constexpr int ROWALIGN = gcd(16, NP * (int)sizeof(T));
@@ -234,7 +236,7 @@ template <typename T, int NP, int CM>
 __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int j, const int seg,
                                            const int lane, T *tab, T *sh) {
   using S_ = Shape<T, NP>;
-  constexpr int N = S_::N, GPW = S_::GPW, SH = S_::SH, NB = S_::NB, TB = S_::TB;
+  constexpr int N = S_::N, GPW = S_::GPW, SH = S_::SH, NB = S_::NB;
   const T *__restrict__ q = A.q;
   const T *q0 = A.q0;
   T *out = A.out;
@@ -299,8 +301,11 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
       for (int k = 0; k < NP; ++k) xS[v][k] = T(0);
   }
   {
+    // one round of 64 lanes up to r = 4 (a single wait, which the state
+    // loads need anyway); the registers of a two-phase copy would push the
+    // FP64 r >= 4 kernels into scratch
     const T *gB = &gt->B[0][0], *gw = &gt->w[0], *rBM = &rt->BM[0][0];
-    for (int k = lane; k < TB; k += 64)
+    for (int k = lane; k < S_::TBU; k += 64)
       tab[k] = k < NP * NP ? gB[k] : (k < NP * NP + NP ? gw[k - NP * NP] : rBM[k - NP * NP - NP]);
   }
 
@@ -550,7 +555,9 @@ struct ShapeH2 {
   static constexpr int rBM = 4 * NP, rDM = rBM + N, rMN = rDM + N, rMS = rMN + NP;
   static constexpr int rTop = rMS + NP, rBot = rTop + 1;
   static constexpr int RP = rBot + 1;                   // values of one RowTab
-  static constexpr int TB = G1 + 2 * RP;
+  // rounded up to whole 64-lane rounds: the copy stores every lane's value
+  // (those past the tables are clamped duplicates, never read)
+  static constexpr int TB = (G1 + 2 * RP + 63) / 64 * 64;
   static constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
   static constexpr int ROWALIGN = gcd(16, NP * (int)sizeof(T));
   // alignment of a half row starting at h K0 (even NP only; odd NP: element)
@@ -661,12 +668,22 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
   const bool fixed = A.alpha_global != 0;
   const T alpha = gt->alpha;
 
+  // the tables read with lane-dependent indices: loaded first and stored to LDS
+  // once the state loads are in flight (a load-store loop would wait for every
+  // load, and for all the state loads issued before it)
+  constexpr int TBU = PK ? S_::TB : S_::G1 + S_::RP;     // the second row only when packed
+  constexpr int TIT = (TBU + 63) / 64;
+  static_assert(TIT * 64 <= S_::TB, "table copy rounds");
+  T tv[TIT];
   {
     const T *g0 = &gt->B[0][0], *ra = &A.rows[j0].cosn[0];
     const T *rb = &A.rows[j0 + 1 < n_lat ? j0 + 1 : j0].cosn[0];
-    constexpr int TBU = PK ? S_::TB : S_::G1 + S_::RP;     // the second row only when packed
-    for (int k = lane; k < TBU; k += 64)
-      tab[k] = k < S_::G1 ? g0[k] : (k < S_::G1 + S_::RP ? ra[k - S_::G1] : rb[k - S_::G1 - S_::RP]);
+#pragma unroll
+    for (int it = 0; it < TIT; ++it) {
+      const int k = lane + 64 * it < TBU ? lane + 64 * it : TBU - 1;   // clamped: read, not stored
+      const T *p = k < S_::G1 ? g0 + k : (k < S_::G1 + S_::RP ? ra + (k - S_::G1) : rb + (k - S_::G1 - S_::RP));
+      tv[it] = *p;
+    }
   }
   // ---- global loads: own row b = t, this half's longitude neighbour row and
   // latitude neighbour column
@@ -687,6 +704,8 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
 #pragma unroll
       for (int k = 0; k < NP; ++k) xY[v][k] = c[v * N + k * NP];
   }
+#pragma unroll
+  for (int it = 0; it < TIT; ++it) tab[lane + 64 * it] = tv[it];
   // per-lane coefficients: rows h K0 + k of B (clamped), this half's own edge
   // (h = 0: +1, h = 1: -1) and the facing edge of its neighbours; from the
   // LDS tables where the registers are tight (SPLIT), else selected from the
