@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "dgsw_ctx.hpp"
 #include "dgsw_device.hpp"
@@ -219,6 +220,7 @@ struct MlpCorrection {           // the learned stage's correction step (FROM_Q)
 };
 constexpr int kWaves = 8;                 // wavefronts per workgroup
 constexpr int kLd = kHidden + 8;          // LDS row stride in BF16 (+16 B: no bank conflicts)
+constexpr int kYs = kRows + 4;            // stride of the network outputs' unit columns in LDS
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 // One hidden layer for the 64 rows of a tile: wavefront wv computes units
@@ -233,7 +235,7 @@ __device__ __forceinline__ void fused_hidden(const bf16x8 (&w)[K / 32][2], const
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = bv[nt];   // the bias, then the products
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
     bf16x8 b[MT];
@@ -253,7 +255,7 @@ __device__ __forceinline__ void fused_hidden(const bf16x8 (&w)[K / 32][2], const
     for (int mt = 0; mt < MT; ++mt) {
       bf16x4 h;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) h[i] = (__bf16)gelu_f(acc[nt][mt][i] + bv[nt][i]);
+      for (int i = 0; i < 4; ++i) h[i] = (__bf16)gelu_f(acc[nt][mt][i]);
       *reinterpret_cast<bf16x4 *>(out + (16 * mt + r) * kLd + n0) = h;
     }
   }
@@ -278,13 +280,13 @@ __device__ __forceinline__ void load_hidden(const __bf16 *__restrict__ Wt, const
 // k_correction: c = mean_j + std_j y with c_(h,00) = 0; rejected (c = 0) if
 // non-finite or, for a variable, max|c| > kappa max|L1|.  Returns whether it
 // fell back and the element's h-mass of the correction.
-template <typename T>
-__device__ __forceinline__ bool correction_row(const float *y, const T *__restrict__ L1e, const float *__restrict__ om,
-                                               const float *__restrict__ os, float kappa, float *c) {
+template <int SY, int SL>
+__device__ __forceinline__ bool correction_row(const float *y, const float *L1e, const float *om, const float *os,
+                                               float kappa, float *c) {
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    c[k] = k == 0 ? 0.f : om[k] + os[k] * y[k];
+    c[k] = k == 0 ? 0.f : om[k * SL] + os[k * SL] * y[k * SY];
     ok = ok && isfinite(c[k]);
   }
 #pragma unroll
@@ -293,7 +295,7 @@ __device__ __forceinline__ bool correction_row(const float *y, const T *__restri
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       mc = fmaxf(mc, fabsf(c[v * 4 + m]));
-      ml = fmaxf(ml, fabsf((float)L1e[v * 4 + m]));
+      ml = fmaxf(ml, fabsf(L1e[(v * 4 + m) * SL]));
     }
     ok = ok && !(mc > kappa * ml);
   }
@@ -322,19 +324,32 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_fused(const T *__restrict__
                                                           MlpCorrection<T> cor) {
   __shared__ __attribute__((aligned(16))) __bf16 buf0[kRows * kLd];
   __shared__ __attribute__((aligned(16))) __bf16 buf1[kRows * kLd];
+  __shared__ __attribute__((aligned(16))) __bf16 st_w3[kOutPad * kLd];
+  // the correction's operands of the tile's rows (FROM_Q): the r = 1
+  // right-hand side, the output mean and spread of the row's latitude (value
+  // k of row i at k kRows + i: the lane-per-row reads hit distinct banks), the
+  // latitude's h-mass weight of mode (0, 1)
+  __shared__ float st_l1[FROM_Q ? kRows * 12 : 1], st_om[FROM_Q ? kRows * 12 : 1], st_os[FROM_Q ? kRows * 12 : 1];
+  __shared__ double st_mw[FROM_Q ? kRows : 1];
+  // the feature standardisation (FROM_Q), once per workgroup
+  __shared__ float st_fm[FROM_Q ? kFeatures : 1], st_fi[FROM_Q ? kFeatures : 1];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r = lane & 15, kq = (lane >> 4) * 8;
-  // the weights, once per workgroup
-  bf16x8 w1[kInPad / 32][2], w2[kHidden / 32][2], w3[kHidden / 32];
+  // the output layer's weights in LDS (rows padded like the activations):
+  // registers held for 8 products per tile would push the kernel into scratch
+  for (int c = tid; c < kOutPad * kHidden / 8; c += 64 * kWaves) {
+    const int u = c / (kHidden / 8), k8 = c - u * (kHidden / 8);
+    *reinterpret_cast<bf16x8 *>(st_w3 + u * kLd + 8 * k8) =
+        *reinterpret_cast<const bf16x8 *>(W3t + (size_t)u * kHidden + 8 * k8);
+  }
+  // the hidden layers' weights in registers, requested after the LDS tables
+  // (loads complete in order: the tables' stores wait only for their own
+  // loads, and these arrive while the first tile's inputs are fetched)
+  bf16x8 w1[kInPad / 32][2], w2[kHidden / 32][2];
   f32x4 bv1[2], bv2[2];
-  load_hidden<kInPad>(W1t, b1, wv, lane, w1, bv1);
-  load_hidden<kHidden>(W2t, b2, wv, lane, w2, bv2);
   // output layer: wavefront wv takes rows [16 (wv / 2), +16) and units [16 (wv % 2), +16)
   const int mt = wv >> 1, nt = wv & 1;
-#pragma unroll
-  for (int ks = 0; ks < kHidden / 32; ++ks)
-    w3[ks] = *reinterpret_cast<const bf16x8 *>(W3t + (size_t)(16 * nt + r) * kHidden + 32 * ks + kq);
   const int n0 = 16 * nt + (lane >> 4) * 4;
   const f32x4 bv3 = *reinterpret_cast<const f32x4 *>(b3p + n0);
   // zero padding of the inputs beyond the 108 features (never overwritten)
@@ -342,71 +357,127 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_fused(const T *__restrict__
     const int rr = idx / (kInPad - kFeatures);
     buf0[rr * kLd + kFeatures + (idx - rr * (kInPad - kFeatures))] = (__bf16)0.f;
   }
+  if constexpr (FROM_Q) {
+    for (int k = tid; k < kFeatures; k += 64 * kWaves) {
+      st_fm[k] = fmean[k];
+      st_fi[k] = fistd[k];
+    }
+  }
+  load_hidden<kInPad>(W1t, b1, wv, lane, w1, bv1);
+  load_hidden<kHidden>(W2t, b2, wv, lane, w2, bv2);
+  __syncthreads();            // the tables above before their first use
   double mass = 0.0;          // wavefront 0: this workgroup's h-mass of the corrections
   bool any_fell = false;
   unsigned long long fell_count = 0ull;
+  // the 12 values of input task (row rr, stencil neighbour sn), raw, and
+  // their BF16 features in buf0
+  using In = typename std::conditional<FROM_Q, T, float>::type;
+  int e0 = 0;
+  auto load_task = [&](int task, In (&x)[12]) {
+    const int rr = task / 9, sn = task - rr * 9;
+    const int e = e0 + rr < rows ? e0 + rr : rows - 1;
+    const In *src;
+    if constexpr (FROM_Q) {
+      const int dj = sn / 3 - 1, di = sn % 3 - 1;
+      const int j = e / n_lon, i = e - j * n_lon;
+      int jj = j + dj;
+      jj = jj < 0 ? 0 : (jj >= n_lat ? n_lat - 1 : jj);
+      int ii = i + di;
+      ii = ii < 0 ? ii + n_lon : (ii >= n_lon ? ii - n_lon : ii);
+      src = q + ((size_t)jj * n_lon + ii) * 12;
+    } else {
+      src = X + (size_t)e * kFeatures + sn * 12;
+    }
+#pragma unroll
+    for (int vm = 0; vm < 12; ++vm) x[vm] = src[vm];
+  };
+  auto store_task = [&](int task, const In (&raw)[12]) {
+    const int rr = task / 9, sn = task - rr * 9;
+    float x[12];
+#pragma unroll
+    for (int vm = 0; vm < 12; ++vm) x[vm] = (float)raw[vm];
+    if constexpr (FROM_Q) {
+#pragma unroll
+      for (int vm = 0; vm < 12; ++vm) x[vm] = (x[vm] - st_fm[sn * 12 + vm]) * st_fi[sn * 12 + vm];
+    }
+    bf16x4 *dst = reinterpret_cast<bf16x4 *>(buf0 + rr * kLd + sn * 12);
+#pragma unroll
+    for (int h4 = 0; h4 < 3; ++h4)
+      dst[h4] = bf16x4{(__bf16)x[4 * h4], (__bf16)x[4 * h4 + 1], (__bf16)x[4 * h4 + 2], (__bf16)x[4 * h4 + 3]};
+  };
   const int ntiles = (rows + kRows - 1) / kRows;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int e0 = tile * kRows;
-    // inputs: one task per (row, stencil neighbour): 12 contiguous values
-    for (int task = tid; task < kRows * 9; task += 64 * kWaves) {
-      const int rr = task / 9, sn = task - rr * 9;
-      const int e = e0 + rr < rows ? e0 + rr : rows - 1;
-      float x[12];
-      if constexpr (FROM_Q) {
-        const int dj = sn / 3 - 1, di = sn % 3 - 1;
-        const int j = e / n_lon, i = e - j * n_lon;
-        int jj = j + dj;
-        jj = jj < 0 ? 0 : (jj >= n_lat ? n_lat - 1 : jj);
-        int ii = i + di;
-        ii = ii < 0 ? ii + n_lon : (ii >= n_lon ? ii - n_lon : ii);
-        const T *src = q + ((size_t)jj * n_lon + ii) * 12;
+    e0 = tile * kRows;
+    // inputs: one task per (row, stencil neighbour), 12 contiguous values;
+    // the 64 tasks beyond one per lane go to wavefront 0, and the correction's
+    // operands of the tile's rows are staged in LDS by wavefronts 1 .. 3, all
+    // loads issued before any is waited for (one memory round trip per tile)
+    constexpr int kTasks = kRows * 9;
+    static_assert(kTasks > 64 * kWaves && kTasks <= 64 * kWaves + 64, "one extra task per lane of wavefront 0");
+    In raw0[12], raw1[12];
+    load_task(tid, raw0);
+    if (wv == 0) load_task(tid + 64 * kWaves, raw1);
+    if constexpr (FROM_Q) {
+      const int e = e0 + lane < rows ? e0 + lane : rows - 1;
+      const int j = e / n_lon;
+      if (wv == 1) {
+        const T *src = cor.L1 + (size_t)e * 12;
+        T l1[12];
 #pragma unroll
-        for (int vm = 0; vm < 12; ++vm) x[vm] = (float)src[vm];
+        for (int k = 0; k < 12; ++k) l1[k] = src[k];
 #pragma unroll
-        for (int vm = 0; vm < 12; ++vm) x[vm] = (x[vm] - fmean[sn * 12 + vm]) * fistd[sn * 12 + vm];
-      } else {
-        const float *src = X + (size_t)e * kFeatures + sn * 12;
+        for (int k = 0; k < 12; ++k) st_l1[k * kRows + lane] = (float)l1[k];
+      } else if (wv == 2) {
+        float om[12], os[12];
 #pragma unroll
-        for (int vm = 0; vm < 12; ++vm) x[vm] = src[vm];
+        for (int k = 0; k < 12; ++k) {
+          om[k] = cor.omean[j * 12 + k];
+          os[k] = cor.ostd[j * 12 + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          st_om[k * kRows + lane] = om[k];
+          st_os[k * kRows + lane] = os[k];
+        }
+      } else if (wv == 3) {
+        st_mw[lane] = cor.mass_w[j * 2 + 1];
       }
-      bf16x4 *dst = reinterpret_cast<bf16x4 *>(buf0 + rr * kLd + sn * 12);
-#pragma unroll
-      for (int h4 = 0; h4 < 3; ++h4)
-        dst[h4] = bf16x4{(__bf16)x[4 * h4], (__bf16)x[4 * h4 + 1], (__bf16)x[4 * h4 + 2], (__bf16)x[4 * h4 + 3]};
     }
+    store_task(tid, raw0);
+    if (wv == 0) store_task(tid + 64 * kWaves, raw1);
     __syncthreads();
     fused_hidden<kInPad>(w1, bv1, buf0, buf1, wv, lane);
     __syncthreads();
     fused_hidden<kHidden>(w2, bv2, buf1, buf0, wv, lane);
     __syncthreads();
-    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    f32x4 acc = bv3;
 #pragma unroll
     for (int ks = 0; ks < kHidden / 32; ++ks) {
       const bf16x8 b = *reinterpret_cast<const bf16x8 *>(buf0 + (16 * mt + r) * kLd + 32 * ks + kq);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3[ks], b, acc, 0, 0, 0);
+      const bf16x8 w3 = *reinterpret_cast<const bf16x8 *>(st_w3 + (16 * nt + r) * kLd + 32 * ks + kq);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, b, acc, 0, 0, 0);
     }
-    const f32x4 out = acc + bv3;
+    const f32x4 out = acc;
     if constexpr (!FROM_Q) {
       const int e = e0 + 16 * mt + r;
       if (e < rows) *reinterpret_cast<f32x4 *>(Y + (size_t)e * kOutPad + n0) = out;
     } else {
       // outputs to LDS (the first hidden layer's buffer is free), then one
       // lane per row forms its element's correction (wavefront 0)
+      // (unit n of row i at n kYs + i: conflict-free stores and lane-per-row reads)
       float *ys = reinterpret_cast<float *>(buf1);
-      *reinterpret_cast<f32x4 *>(ys + (16 * mt + r) * kOutPad + n0) = out;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ys[(n0 + i) * kYs + 16 * mt + r] = out[i];
       __syncthreads();
       if (wv == 0) {
         const int e = e0 + lane;
         double m = 0.0;
         bool fell = false;
         if (e < rows) {
-          const int j = e / n_lon;
           float c[12];
-          fell = correction_row<T>(ys + lane * kOutPad, cor.L1 + (size_t)e * 12, cor.omean + j * 12,
-                                   cor.ostd + j * 12, cor.kappa, c);
+          fell = correction_row<kYs, kRows>(ys + lane, st_l1 + lane, st_om + lane, st_os + lane, cor.kappa, c);
           // h-mass of the correction: modes (a, b) = (0, 0) and (0, 1), i.e. 0 and 2
-          m = cor.mass_w[j * 2 + 1] * (double)c[2];
+          m = st_mw[lane] * (double)c[2];
           float4 *cd = reinterpret_cast<float4 *>(cor.C + (size_t)e * 12);
 #pragma unroll
           for (int k4 = 0; k4 < 3; ++k4) cd[k4] = make_float4(c[4 * k4], c[4 * k4 + 1], c[4 * k4 + 2], c[4 * k4 + 3]);
