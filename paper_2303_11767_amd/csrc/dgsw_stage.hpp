@@ -497,7 +497,10 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
     for (int a = 0; a < NP; ++a) {
       T acc = T(0);
 #pragma unroll
-      for (int p = 0; p < NP; ++p) acc += gt->D[p][a] * zd[p] + gt->B[p][a] * zb[p];
+      for (int p = 0; p < NP; ++p) {   // two chained FMAs (a sum of products first costs a third instruction)
+        acc += gt->D[p][a] * zd[p];
+        acc += gt->B[p][a] * zb[p];
+      }
       acc -= cF * (gt->Pp[a] * XE - gt->Pm[a] * XW);
       acc += fr[v][a];
       if (combine == 2) {
@@ -931,7 +934,9 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
     for (int kb = 0; kb < K0; ++kb) {
       if (NP % 2 != 0 && h * K0 + kb >= NP) continue;   // the odd-order tail slot
       const int b = bh[kb];
-      const T zg = ZG[v][kb] - (GhN[v] * tab[ro + S_::rMN + b] - GhS[v] * tab[ro + S_::rMS + b]);
+      T zg = ZG[v][kb];
+      zg -= GhN[v] * tab[ro + S_::rMN + b];
+      zg += GhS[v] * tab[ro + S_::rMS + b];
       const T zs = v == 0 ? T(0) : ZS[v - 1][kb];
       S[((v * 2 + 0) * NP + t) * NP + b] = cF * wt * ZD[v][kb];
       S[((v * 2 + 1) * NP + t) * NP + b] = wt * (cG * zg + zs);
@@ -990,7 +995,10 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
     for (int k = 0; k < K0; ++k) {
       T acc = T(0);
 #pragma unroll
-      for (int p = 0; p < NP; ++p) acc += DA[p][k] * zd[p] + BA[p][k] * zb[p];
+      for (int p = 0; p < NP; ++p) {   // two chained FMAs (a sum of products first costs a third instruction)
+        acc += DA[p][k] * zd[p];
+        acc += BA[p][k] * zb[p];
+      }
       acc -= cF * (PpA[k] * XE - PmA[k] * XW);
       acc += fh[v][k];
       if (combine == 2) {
