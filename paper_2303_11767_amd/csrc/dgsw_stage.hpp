@@ -437,7 +437,9 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
   for (int v = 0; v < 3; ++v)
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
-      const T zg = ZG[v][b] - (GhN[v] * rt->MN[b] - GhS[v] * rt->MS[b]);
+      T zg = ZG[v][b];
+      zg -= GhN[v] * rt->MN[b];
+      zg += GhS[v] * rt->MS[b];
       const T zs = v == 0 ? T(0) : ZS[v - 1][b];
       S[((v * 2 + 0) * NP + t) * NP + b] = cF * wt * ZD[v][b];
       S[((v * 2 + 1) * NP + t) * NP + b] = wt * (cG * zg + zs);
@@ -493,16 +495,18 @@ __device__ __forceinline__ void stage_wave(const StageArgs<T, NP> &A, const int 
     if (combine == 2 && A.qa) load_row<T, NP>(A.qa + base + v * N, xa);
     if (combine == 2 && A.qb) load_row<T, NP>(A.qb + base + v * N, xb);
     T res[NP];
+    const T cXE = cF * XE, cXW = cF * XW;
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-      T acc = T(0);
+      // the forcing, then chained FMAs (a sum of products first costs a third instruction)
+      T acc = fr[v][a];
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {   // two chained FMAs (a sum of products first costs a third instruction)
+      for (int p = 0; p < NP; ++p) {
         acc += gt->D[p][a] * zd[p];
         acc += gt->B[p][a] * zb[p];
       }
-      acc -= cF * (gt->Pp[a] * XE - gt->Pm[a] * XW);
-      acc += fr[v][a];
+      acc -= gt->Pp[a] * cXE;
+      acc += gt->Pm[a] * cXW;
       if (combine == 2) {
         const T b0 = q0r[v][a];
         res[a] = b0 + dt * acc + (c1 * (qr[v][a] - b0) + (A.ca * (xa[a] - b0) + A.cb * (xb[a] - b0)));
@@ -991,16 +995,18 @@ __device__ __forceinline__ void stage_wave_h2(const StageArgs<T, NP> &A, const i
     if (combine == 2 && A.qa) load_half<T, NP>(A.qa + ebase + v * N, h, xa);
     if (combine == 2 && A.qb) load_half<T, NP>(A.qb + ebase + v * N, h, xb);
     T res[K0];
+    const T cXE = cF * XE, cXW = cF * XW;
 #pragma unroll
     for (int k = 0; k < K0; ++k) {
-      T acc = T(0);
+      // the forcing, then chained FMAs (a sum of products first costs a third instruction)
+      T acc = fh[v][k];
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {   // two chained FMAs (a sum of products first costs a third instruction)
+      for (int p = 0; p < NP; ++p) {
         acc += DA[p][k] * zd[p];
         acc += BA[p][k] * zb[p];
       }
-      acc -= cF * (PpA[k] * XE - PmA[k] * XW);
-      acc += fh[v][k];
+      acc -= PpA[k] * cXE;
+      acc += PmA[k] * cXW;
       if (combine == 2) {
         const T b0 = q0h[v][k];
         res[k] = b0 + dt * acc + (c1 * (qh[v][k] - b0) + (A.ca * (xa[k] - b0) + A.cb * (xb[k] - b0)));
