@@ -45,9 +45,10 @@ struct Carve {
   }
 };
 
-// BF16 weights for the forward pass (and the backward pass when Wr != null)
+// BF16 weights for the forward pass (and the backward pass when Wr != null);
+// the hidden layers' also in the fused network kernel's fragment order
 struct Weights {
-  __bf16 *W1t, *W2t, *W3t, *W1r, *W2r, *W3r;
+  __bf16 *W1t, *W2t, *W3t, *W1r, *W2r, *W3r, *W1f, *W2f;
   float *b3p;
 };
 
@@ -59,15 +60,20 @@ Weights carve_weights(Carve &c, bool backward) {
   w.W1r = backward ? c.take<__bf16>((size_t)kInPad * kHidden) : nullptr;
   w.W2r = backward ? c.take<__bf16>((size_t)kHidden * kHidden) : nullptr;
   w.W3r = backward ? c.take<__bf16>((size_t)kHidden * kOutPad) : nullptr;
+  w.W1f = c.take<__bf16>((size_t)kHidden * kInPad);
+  w.W2f = c.take<__bf16>((size_t)kHidden * kHidden);
   w.b3p = c.take<float>(kOutPad);
   return w;
 }
 
 hipError_t prep(const float *P, const Weights &w, hipStream_t s) {
   hipError_t e;
-  if ((e = dgsw::launch_prep_weights(P + oW1, kFeatures, kHidden, kInPad, kHidden, w.W1t, w.W1r, s)) != hipSuccess) return e;
-  if ((e = dgsw::launch_prep_weights(P + oW2, kHidden, kHidden, kHidden, kHidden, w.W2t, w.W2r, s)) != hipSuccess) return e;
-  if ((e = dgsw::launch_prep_weights(P + oW3, kHidden, kOut, kHidden, kOutPad, w.W3t, w.W3r, s)) != hipSuccess) return e;
+  if ((e = dgsw::launch_prep_weights(P + oW1, kFeatures, kHidden, kInPad, kHidden, w.W1t, w.W1r, w.W1f, s)) != hipSuccess)
+    return e;
+  if ((e = dgsw::launch_prep_weights(P + oW2, kHidden, kHidden, kHidden, kHidden, w.W2t, w.W2r, w.W2f, s)) != hipSuccess)
+    return e;
+  if ((e = dgsw::launch_prep_weights(P + oW3, kHidden, kOut, kHidden, kOutPad, w.W3t, w.W3r, nullptr, s)) != hipSuccess)
+    return e;
   return dgsw::launch_pad(P + ob3, kOut, kOutPad, w.b3p, s);
 }
 
@@ -172,7 +178,7 @@ int dg_mlp_forward(const float *params, const float *X, int64_t rows, float *Y, 
   TrainWs t = carve_train(workspace, rows, nullptr);
   hipError_t e;
   if ((e = prep(params, t.w, s)) != hipSuccess) return hip_fail(e, "weight preparation");
-  if ((e = dgsw::launch_mlp_fused(0, nullptr, 0, 0, nullptr, nullptr, X, (int)rows, t.w.W1t, t.w.W2t, t.w.W3t,
+  if ((e = dgsw::launch_mlp_fused(0, nullptr, 0, 0, nullptr, nullptr, X, (int)rows, t.w.W1f, t.w.W2f, t.w.W3t,
                                   params + ob1, params + ob2, t.w.b3p, t.Y, s, nullptr)) != hipSuccess)
     return hip_fail(e, "forward");
   if ((e = dgsw::launch_unpad(t.Y, (int)rows, kOut, kOutPad, Y, s)) != hipSuccess) return hip_fail(e, "output");
@@ -309,7 +315,7 @@ int learned_stage(dg_ctx *ctx, const dg_learned *net, const LearnWs &t, const vo
   ca.L1 = t.L1; ca.omean = net->out_mean; ca.ostd = net->out_std; ca.mass_w = ctx->d_mass_w;
   ca.kappa = (float)net->kappa; ca.C = t.C; ca.partial = t.partial; ca.fallback = fallbacks;
   if ((e = dgsw::launch_mlp_fused(dt_, q, ctx->d.n_lon, ctx->d.n_lat, net->feat_mean, net->feat_istd, nullptr,
-                                  ctx->E, t.w.W1t, t.w.W2t, t.w.W3t, net->params + ob1, net->params + ob2, t.w.b3p,
+                                  ctx->E, t.w.W1f, t.w.W2f, t.w.W3t, net->params + ob1, net->params + ob2, t.w.b3p,
                                   nullptr, s, &ca)) != hipSuccess)
     return hip_fail(e, "network launch");
   dgsw::LearnedOut l;

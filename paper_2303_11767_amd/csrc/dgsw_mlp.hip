@@ -261,17 +261,17 @@ __device__ __forceinline__ void fused_hidden(const bf16x8 (&w)[K / 32][2], const
   }
 }
 
-// This wavefront's weight fragments of a hidden layer (units 32 wv ..) and
-// the matching biases.
+// This wavefront's weight fragments of a hidden layer (units 32 wv ..), from
+// the fragment order Wf (one contiguous kilobyte per load), and the matching
+// biases.
 template <int K>
-__device__ __forceinline__ void load_hidden(const __bf16 *__restrict__ Wt, const float *__restrict__ bias, int wv,
+__device__ __forceinline__ void load_hidden(const __bf16 *__restrict__ Wf, const float *__restrict__ bias, int wv,
                                             int lane, bf16x8 (&w)[K / 32][2], f32x4 (&bv)[2]) {
-  const int r = lane & 15, kq = (lane >> 4) * 8;
 #pragma unroll
   for (int nt = 0; nt < 2; ++nt) {
-    const __bf16 *row = Wt + (size_t)(32 * wv + 16 * nt + r) * K + kq;
+    const __bf16 *blk = Wf + (size_t)(2 * wv + nt) * (K / 32) * 512 + lane * 8;
 #pragma unroll
-    for (int ks = 0; ks < K / 32; ++ks) w[ks][nt] = *reinterpret_cast<const bf16x8 *>(row + 32 * ks);
+    for (int ks = 0; ks < K / 32; ++ks) w[ks][nt] = *reinterpret_cast<const bf16x8 *>(blk + 512 * ks);
     bv[nt] = *reinterpret_cast<const f32x4 *>(bias + 32 * wv + 16 * nt + (lane >> 4) * 4);
   }
 }
@@ -316,8 +316,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_fused(const T *__restrict__
                                                           const float *__restrict__ fmean,
                                                           const float *__restrict__ fistd,
                                                           const float *__restrict__ X, int rows,
-                                                          const __bf16 *__restrict__ W1t,
-                                                          const __bf16 *__restrict__ W2t,
+                                                          const __bf16 *__restrict__ W1f,
+                                                          const __bf16 *__restrict__ W2f,
                                                           const __bf16 *__restrict__ W3t,
                                                           const float *__restrict__ b1, const float *__restrict__ b2,
                                                           const float *__restrict__ b3p, float *__restrict__ Y,
@@ -363,8 +363,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_fused(const T *__restrict__
       st_fi[k] = fistd[k];
     }
   }
-  load_hidden<kInPad>(W1t, b1, wv, lane, w1, bv1);
-  load_hidden<kHidden>(W2t, b2, wv, lane, w2, bv2);
+  load_hidden<kInPad>(W1f, b1, wv, lane, w1, bv1);
+  load_hidden<kHidden>(W2f, b2, wv, lane, w2, bv2);
   __syncthreads();            // the tables above before their first use
   double mass = 0.0;          // wavefront 0: this workgroup's h-mass of the corrections
   bool any_fell = false;
@@ -508,7 +508,7 @@ int mlp_fused_blocks(int rows) {
 }
 
 hipError_t launch_mlp_fused(int dtype, const void *q, int n_lon, int n_lat, const float *fmean, const float *fistd,
-                            const float *X, int rows, const __bf16 *W1t, const __bf16 *W2t, const __bf16 *W3t,
+                            const float *X, int rows, const __bf16 *W1f, const __bf16 *W2f, const __bf16 *W3t,
                             const float *b1, const float *b2, const float *b3p, float *Y, hipStream_t s,
                             const CorrectionArgs *ca) {
   static_assert(kInPad % 32 == 0 && kHidden == 32 * kWaves && kOutPad == 32 && kRows == 8 * kWaves,
@@ -516,8 +516,8 @@ hipError_t launch_mlp_fused(int dtype, const void *q, int n_lon, int n_lat, cons
   if (rows <= 0) return hipSuccess;
   const dim3 grid(mlp_fused_blocks(rows)), block(64 * kWaves);
   if (!q) {
-    hipLaunchKernelGGL((k_mlp_fused<float, false>), grid, block, 0, s, nullptr, 0, 0, nullptr, nullptr, X, rows, W1t,
-                       W2t, W3t, b1, b2, b3p, Y, MlpCorrection<float>{});
+    hipLaunchKernelGGL((k_mlp_fused<float, false>), grid, block, 0, s, nullptr, 0, 0, nullptr, nullptr, X, rows, W1f,
+                       W2f, W3t, b1, b2, b3p, Y, MlpCorrection<float>{});
     return hipGetLastError();
   }
   if (!ca) return hipErrorInvalidValue;
@@ -525,12 +525,12 @@ hipError_t launch_mlp_fused(int dtype, const void *q, int n_lon, int n_lat, cons
     MlpCorrection<double> c{static_cast<const double *>(ca->L1), ca->omean, ca->ostd, ca->mass_w, ca->kappa, ca->C,
                             ca->partial, ca->fallback};
     hipLaunchKernelGGL((k_mlp_fused<double, true>), grid, block, 0, s, static_cast<const double *>(q), n_lon, n_lat,
-                       fmean, fistd, nullptr, rows, W1t, W2t, W3t, b1, b2, b3p, Y, c);
+                       fmean, fistd, nullptr, rows, W1f, W2f, W3t, b1, b2, b3p, Y, c);
   } else {
     MlpCorrection<float> c{static_cast<const float *>(ca->L1), ca->omean, ca->ostd, ca->mass_w, ca->kappa, ca->C,
                            ca->partial, ca->fallback};
     hipLaunchKernelGGL((k_mlp_fused<float, true>), grid, block, 0, s, static_cast<const float *>(q), n_lon, n_lat,
-                       fmean, fistd, nullptr, rows, W1t, W2t, W3t, b1, b2, b3p, Y, c);
+                       fmean, fistd, nullptr, rows, W1f, W2f, W3t, b1, b2, b3p, Y, c);
   }
   return hipGetLastError();
 }
@@ -538,9 +538,14 @@ hipError_t launch_mlp_fused(int dtype, const void *q, int n_lon, int n_lat, cons
 // ------------------------------------------------------------------ weights
 // FP32 parameter vector -> BF16 operand copies: Wt[n][kp] (forward, k
 // contiguous, k padded with zeros to kp) and Wr[k][np] (backward, rows padded
-// to the next layer's padded width np, columns beyond n zero).
+// to the next layer's padded width np, columns beyond n zero), and Wf, the
+// forward weights in the order the fused kernel's wavefronts read them: for
+// units [16 u, 16 u + 16) and inputs [32 c, 32 c + 32) one 1 KB block,
+// ((u K/32 + c) 64 + lane) 8 + j holding unit 16 u + lane % 16 and input
+// 32 c + 8 (lane / 16) + j (the MFMA A-operand layout), so that each of its
+// loads is one contiguous kilobyte (kp % 32 == 0, np % 16 == 0).
 __global__ void k_prep_weights(const float *__restrict__ W, int k_in, int n_out, int kp, int np_,
-                               __bf16 *__restrict__ Wt, __bf16 *__restrict__ Wr) {
+                               __bf16 *__restrict__ Wt, __bf16 *__restrict__ Wr, __bf16 *__restrict__ Wf) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = kp * np_;
   if (idx >= total) return;
@@ -548,12 +553,18 @@ __global__ void k_prep_weights(const float *__restrict__ W, int k_in, int n_out,
   const float w = (k < k_in && n < n_out) ? W[(size_t)k * n_out + n] : 0.0f;
   if (Wr) Wr[(size_t)k * np_ + n] = (__bf16)w;
   if (Wt) Wt[(size_t)n * kp + k] = (__bf16)w;
+  if (Wf) {
+    const int lane = n % 16 + 16 * ((k % 32) / 8);
+    Wf[((size_t)(n / 16) * (kp / 32) + k / 32) * 512 + lane * 8 + k % 8] = (__bf16)w;
+  }
 }
 
 hipError_t launch_prep_weights(const float *W, int k_in, int n_out, int kp, int np_, __bf16 *Wt, __bf16 *Wr,
-                               hipStream_t s) {
+                               __bf16 *Wf, hipStream_t s) {
+  if (Wf && (kp % 32 || np_ % 16)) return hipErrorInvalidValue;
   const int total = kp * np_;
-  hipLaunchKernelGGL(k_prep_weights, dim3((total + 255) / 256), dim3(256), 0, s, W, k_in, n_out, kp, np_, Wt, Wr);
+  hipLaunchKernelGGL(k_prep_weights, dim3((total + 255) / 256), dim3(256), 0, s, W, k_in, n_out, kp, np_, Wt, Wr,
+                     Wf);
   return hipGetLastError();
 }
 

@@ -45,13 +45,15 @@ int mlp_fused_blocks(int rows);
 // Whole-network inference, tiles of 64 rows, activations in LDS.  With q:
 // rows = elements of the r = 1 state q (dtype 0/1), features computed from q,
 // then the correction of each element (ca required; Y unused).  With q == NULL:
-// rows of X[rows][108] (FP32) -> Y[rows][32] FP32 (the first 12 used).
+// rows of X[rows][108] (FP32) -> Y[rows][32] FP32 (the first 12 used).  W1f,
+// W2f: the hidden layers' weights in fragment order (launch_prep_weights' Wf),
+// W3t: the output layer's as Wt.
 hipError_t launch_mlp_fused(int dtype, const void *q, int n_lon, int n_lat, const float *fmean, const float *fistd,
-                            const float *X, int rows, const __bf16 *W1t, const __bf16 *W2t, const __bf16 *W3t,
+                            const float *X, int rows, const __bf16 *W1f, const __bf16 *W2f, const __bf16 *W3t,
                             const float *b1, const float *b2, const float *b3p, float *Y, hipStream_t s,
                             const CorrectionArgs *ca);
 hipError_t launch_prep_weights(const float *W, int k_in, int n_out, int kp, int np_, __bf16 *Wt, __bf16 *Wr,
-                               hipStream_t s);
+                               __bf16 *Wf, hipStream_t s);
 hipError_t launch_mse_grad(const float *Y, const float *T, unsigned mask_bits, int rows, int n_out, int ld,
                            float scale, __bf16 *dY, float *dYf, float *partial, int *nblocks, hipStream_t s);
 // column sums over rows (partial: colsum_chunks(rows) * n floats)
