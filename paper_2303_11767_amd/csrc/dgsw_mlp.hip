@@ -194,10 +194,11 @@ hipError_t launch_gemm(bool a_kc, bool b_kc, int epi, const GemmArgs &g, hipStre
 // ------------------------------------------------------------------ fused inference
 // The whole network in one persistent kernel: one workgroup of 8 wavefronts
 // per compute unit, looping over tiles of 64 rows.  Each wavefront loads its
-// slice of the three weight matrices into registers once (32 units of both
-// hidden layers, 16 outputs over a quarter of the output layer's rows) and
-// keeps them for every tile, so the weights cross the cache hierarchy once
-// per workgroup instead of once per 64 rows.  Per tile the BF16 inputs
+// slice of the two hidden layers' weights into registers once (32 units of
+// each, from the fragment order of k_prep_weights: one contiguous kilobyte
+// per load) and keeps them for every tile, the output layer's weights are
+// copied to LDS, so the weights cross the cache hierarchy once per workgroup
+// instead of once per 64 rows.  Per tile the BF16 inputs
 // (stencil features computed from an r = 1 state, or given FP32 rows) and
 // both hidden layers stay in LDS; only the inputs and the FP32 outputs touch
 // global memory.  Each product is computed transposed, out^T = W in^T: the
