@@ -148,13 +148,38 @@ static hipError_t gemm_t(const GemmArgs &g, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Sum of nsplit partial products part[z][n] over z in order (deterministic).
-__global__ void k_sum_split(const float *__restrict__ part, int nsplit, int n, float *__restrict__ out) {
+// Sum of nsplit partial products part[z][n] over z in order (deterministic):
+// four consecutive outputs per thread, the loads of several z in flight.
+__global__ void k_sum_split(const float *__restrict__ part, int nsplit, int n4, float *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n4) return;
+  const float4 *p = reinterpret_cast<const float4 *>(part) + i;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 8
+  for (int z = 0; z < nsplit; ++z) {
+    const float4 v = p[(size_t)z * n4];
+    acc.x += v.x;
+    acc.y += v.y;
+    acc.z += v.z;
+    acc.w += v.w;
+  }
+  reinterpret_cast<float4 *>(out)[i] = acc;
+}
+// the same one output per thread (n not a multiple of 4, or unaligned)
+__global__ void k_sum_split1(const float *__restrict__ part, int nsplit, int n, float *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float acc = 0.f;
   for (int z = 0; z < nsplit; ++z) acc += part[(size_t)z * n + i];
   out[i] = acc;
+}
+
+hipError_t launch_sum_split(const float *part, int nsplit, int n, float *out, hipStream_t s) {
+  if (n % 4 == 0 && reinterpret_cast<uintptr_t>(part) % 16 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0)
+    hipLaunchKernelGGL(k_sum_split, dim3((n / 4 + 255) / 256), dim3(256), 0, s, part, nsplit, n / 4, out);
+  else
+    hipLaunchKernelGGL(k_sum_split1, dim3((n + 255) / 256), dim3(256), 0, s, part, nsplit, n, out);
+  return hipGetLastError();
 }
 
 int gemm_splits(int K) {
@@ -173,10 +198,7 @@ hipError_t launch_gemm_splitk(const GemmArgs &g, float *partial, hipStream_t s) 
                      p.ldb, p.bias, p.Zin, p.Zout, p.C, p.ldc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int n = g.M * g.ldc;
-  hipLaunchKernelGGL(k_sum_split, dim3((n + 255) / 256), dim3(256), 0, s, partial, z, n,
-                     static_cast<float *>(g.C));
-  return hipGetLastError();
+  return launch_sum_split(partial, z, g.M * g.ldc, static_cast<float *>(g.C), s);
 }
 
 hipError_t launch_gemm(bool a_kc, bool b_kc, int epi, const GemmArgs &g, hipStream_t s) {
@@ -611,7 +633,7 @@ hipError_t launch_mse_grad(const float *Y, const float *T, unsigned mask_bits, i
 // Column sums of G[rows][ld] for the first n columns (bias gradients) in two
 // deterministic passes: workgroup (column block, chunk) sums its chunk of
 // rows for 64 columns (4 row lanes per column, then a fixed tree), and
-// k_sum_split adds the chunks in order.
+// launch_sum_split adds the chunks in order.
 __global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ G, int rows, int n, int ld,
                                                      int chunk, float *__restrict__ part) {
   __shared__ float sh[4][64];
@@ -637,8 +659,7 @@ hipError_t launch_colsum(const float *G, int rows, int n, int ld, float *part, f
   hipLaunchKernelGGL(k_colsum_part, dim3((n + 63) / 64, chunks), dim3(256), 0, s, G, rows, n, ld, chunk, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sum_split, dim3((n + 255) / 256), dim3(256), 0, s, part, chunks, n, out);
-  return hipGetLastError();
+  return launch_sum_split(part, chunks, n, out, s);
 }
 
 // scale * (sum of `n` partials), single block, fixed order, into *out.
