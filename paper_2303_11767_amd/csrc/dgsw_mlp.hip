@@ -841,15 +841,27 @@ __global__ __launch_bounds__(256) void k_learned_out(const T *__restrict__ q, co
                                                      int nparts, double area, int E, int combine, T c0, T ce, T dt,
                                                      T *out) {
   __shared__ double sh[256];
-  const double delta = block_mass_delta(partial, nparts, area, sh);
+  // the element's operands first, so that their loads are in flight while
+  // the block sums the mass partials (the same arithmetic either way)
   const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= E * 12) return;
+  const bool live = idx < E * 12;
   const int k = idx % 12;
-  const T corr = k == 0 ? (T)delta : (T)C[idx];
-  const T l = L1[idx] + corr;
+  T l1v = T(0), qv = T(0), qn = T(0);
+  float cv = 0.f;
+  if (live) {
+    l1v = L1[idx];
+    if (k != 0) cv = C[idx];
+    if (combine) {
+      qv = q[idx];
+      if (c0 != T(0)) qn = q0[idx];
+    }
+  }
+  const double delta = block_mass_delta(partial, nparts, area, sh);
+  if (!live) return;
+  const T corr = k == 0 ? (T)delta : (T)cv;
+  const T l = l1v + corr;
   if (combine) {
-    const T qn = c0 != T(0) ? q0[idx] : T(0);
-    const T y = q[idx] + dt * l;
+    const T y = qv + dt * l;
     out[idx] = y + c0 * (qn - y) + ce * y;
   } else {
     out[idx] = l;
